@@ -1,0 +1,202 @@
+/*
+ * vx.h -- C ABI of libvx.so, the MI355X (gfx950) vortex-core extraction library.
+ *
+ * Method: Liu, Xiong & Liu, "Vectorizing Quantum Turbulence Vortex-Core Lines for Real-Time
+ * Visualization" (arXiv 1911.12070). Given a complex wavefunction psi sampled on a 3D grid, the
+ * library computes
+ *   - the circulation of the phase around every unit face of the grid (Sec. 2.2, circulation
+ *     equation; |C| = 2 pi where a core pierces the face, sign by the right-hand rule of
+ *     Sec. 3.4), as an exact winding number w in {-1, 0, +1};
+ *   - the lists of pierced faces and pierced cells (the vortex nodes and their links of
+ *     Sec. 3.1, in dual form);
+ *   - one sub-grid core sample per listed cell: the mean-position estimate (Sec. 3.3.1) refined
+ *     by minimising |psi|^2 in the plane normal to the pseudo-vorticity (Sec. 3.3.3), with psi
+ *     linearly interpolated between nodes (Sec. 5).
+ *
+ * Conventions
+ *   Grid       node (i,j,k), 0 <= i < nx etc., linear id n = i + nx*(j + ny*k) (x fastest).
+ *   psi        complex64, interleaved (re, im), nx*ny*nz values in node order, device memory,
+ *              16-byte aligned. Values must be finite.
+ *   Periodic   bit a of vx_dims.periodic makes axis a periodic (index nx wraps to 0). On a
+ *              non-periodic axis the faces and cells that would need index n_a do not exist:
+ *              their windings are 0 and they are never listed.
+ *   Faces      face (n, a) is the unit square at node n with normal +e_a (a=0 yz-face, a=1
+ *              zx-face, a=2 xy-face); id = 3*n + a; winding counted about +e_a.
+ *   Cells      cell n is the unit cube with min corner n; id = n. A cell is pierced if any of
+ *              its six faces has w != 0. Descriptor (12 bits): 2-bit two's complement windings
+ *              (01 = +1, 11 = -1) of the faces -x,+x,-y,+y,-z,+z = w_x(n), w_x(n+ex), w_y(n),
+ *              w_y(n+ey), w_z(n), w_z(n+ez), lowest bits first, each about +e_axis.
+ *   Packed     one byte per node: bits 1:0 w_x(n), 3:2 w_y(n), 5:4 w_z(n) (2-bit two's
+ *              complement), bit 6 = cell n pierced, bit 7 = 0.
+ *
+ * Memory and streams
+ *   Every buffer argument named d_* is device memory owned by the caller. The library owns only
+ *   its handle and the handle's small internal state; vx_destroy frees them. All compute calls
+ *   are asynchronous on the given stream (NULL = the device's null stream). Argument errors are
+ *   detected on the host before anything is launched. A handle belongs to one device and must
+ *   not be used by two threads at once.
+ *
+ * Errors
+ *   Every call returns vx_status. Nothing throws, exits or prints. vx_last_error() gives the
+ *   detail of the handle's last failure.
+ */
+#ifndef VX_H
+#define VX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VX_OK = 0,
+    VX_ERR_INVALID = -1,     /* bad argument: null pointer, bad dims, bad sizes */
+    VX_ERR_CAPACITY = -2,    /* an output list was too small (true counts were still written) */
+    VX_ERR_DEVICE = -3,      /* a HIP call failed */
+    VX_ERR_NOMEM = -4,       /* host or device allocation failed */
+    VX_ERR_UNSUPPORTED = -5  /* valid request outside what this build supports */
+} vx_status;
+
+typedef struct vx_handle vx_handle;
+typedef void *vx_stream; /* a hipStream_t */
+
+typedef struct {
+    int32_t nx, ny, nz;
+    uint32_t periodic; /* bit 0: x, bit 1: y, bit 2: z */
+} vx_dims;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int vx_version(void);
+
+/* Create a handle bound to HIP device `device`. *out receives the handle. */
+vx_status vx_create(int device, vx_handle **out);
+/* Destroy a handle. NULL is accepted. Waits for nothing: the caller synchronises its streams. */
+vx_status vx_destroy(vx_handle *h);
+/* Static text of a status code. */
+const char *vx_status_str(int status);
+/* Detail of the handle's last failure ("" if none). Valid until the next call on the handle. */
+const char *vx_last_error(const vx_handle *h);
+
+/* ------------------------------------------------------------------------------------------
+ * Synthetic inputs (support: the paper's simulation data is replaced by seeded fields).
+ * ---------------------------------------------------------------------------------------- */
+
+/* Random-wave tangle psi(x) = sum_k c_k T[(ax_k x + ay_k y + az_k z) mod M], T[m] = exp(2 pi i m/M),
+ * evaluated in FP64 in wave order with one rounding per operation and rounded to complex64.
+ * Arrays are device memory: d_ax, d_ay, d_az uint32[nwaves] (each < table_size), d_coef
+ * double[2*nwaves] (re, im), d_table double[2*table_size]. table_size <= 46340. */
+typedef struct {
+    int32_t nwaves;
+    uint32_t table_size;
+    const uint32_t *d_ax, *d_ay, *d_az;
+    const double *d_coef;
+    const double *d_table;
+} vx_tangle;
+vx_status vx_gen_tangle(vx_handle *h, vx_dims dims, const vx_tangle *t, void *d_psi, vx_stream s);
+
+/* Straight z-line (winding +1) times a ring in the plane z = ring_cz (winding -1 about its
+ * azimuthal direction), core profile d / sqrt(d^2 + 2 xi^2), minimum-image displacements, plus
+ * optional noise d_noise (float[2*N], nullable). FP64 arithmetic rounded to complex64. */
+typedef struct {
+    double line_x, line_y, ring_cx, ring_cy, ring_cz, radius, xi;
+} vx_line_ring;
+vx_status vx_gen_line_ring(vx_handle *h, vx_dims dims, const vx_line_ring *p, const float *d_noise,
+                           void *d_psi, vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
+ * Winding + compaction (Sec. 2.2 circulation, Sec. 3.1 vortex-node graph in dual form).
+ *
+ * The winding of a face is the exact winding number, about the point q = (-delta, +eps)
+ * (0 < eps << delta << 1), of the image of the face's boundary under psi with straight edges:
+ * an edge a->b counts +1 if Im a <= 0 < Im b and Re a Im b - Im a Re b >= 0, -1 if
+ * Im a > 0 >= Im b and Re a Im b - Im a Re b <= 0. The determinant sign is exact (FP32 products
+ * formed in FP64). Results are bit-identical to any exact implementation of this definition.
+ *
+ * Outputs (all device memory, caller-owned):
+ *   d_wind       uint8[N] packed field, or NULL to skip it.
+ *   d_faces      uint64[face_cap] pierced face ids;  d_face_sign int8[face_cap] their w (+1/-1).
+ *   d_cells      uint64[cell_cap] pierced cell ids;  d_cell_desc uint16[cell_cap] descriptors.
+ *   d_counts     int64[2]: true number of pierced faces, cells. Written even on overflow; only
+ *                the first *_cap entries are stored. The call zeroes d_counts first.
+ * Lists are sets: their order is unspecified and may differ between runs. Sort to compare.
+ * The caller detects overflow by comparing d_counts with the capacities after synchronising.
+ * d_faces/d_face_sign may be NULL when face_cap == 0 (likewise cells).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    uint8_t *d_wind;
+    uint64_t *d_faces;
+    int8_t *d_face_sign;
+    int64_t face_cap;
+    uint64_t *d_cells;
+    uint16_t *d_cell_desc;
+    int64_t cell_cap;
+    int64_t *d_counts;
+} vx_winding_out;
+vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_winding_out *out,
+                     vx_stream s);
+
+/* Tile shape of the winding kernel on this handle: rows_per_wave in {1, 2, 4} (0 = default 1),
+ * zchunk = planes marched per workgroup (0 = chosen from the grid size). Results do not depend on
+ * it. nx must be a multiple of 4 for vx_winding (VX_ERR_UNSUPPORTED otherwise). */
+vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk);
+
+/* ------------------------------------------------------------------------------------------
+ * Core-sample refinement (Sec. 3.3.1 mean estimate, Sec. 3.3.3 density-guided minimisation).
+ *
+ * For listed cell i (i < min(*d_count, cap)): x0 = mean of the centres of its pierced faces;
+ * t = grad Re psi x grad Im psi at x0 (fallback: the cell's face flux); in the plane through x0
+ * normal to t, gradient descent of |psi|^2 (trilinear psi) from x0 with a halving step rule,
+ * then a Newton polish on (Re psi, Im psi); trial points must stay inside the cell's 4x4x4
+ * node patch. FP32 arithmetic. d_count is read on the device (no host synchronisation).
+ * d_seed_off (float[3*cap], nullable) replaces x0 by caller seeds (cell-local coordinates).
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_descent;   /* accepted descent steps (32) */
+    int32_t max_newton;    /* Newton steps (20) */
+    int32_t max_halvings;  /* step halvings per trial (30) */
+    float step0;           /* first descent step length, cells (0.25) */
+    float step_max;        /* largest descent step length, cells (1.0) */
+    float armijo;          /* sufficient-decrease constant (1e-4) */
+    float descent_tol;     /* descent stops after an accepted step shorter than this (1e-2) */
+    float newton_tol;      /* Newton stops after a step shorter than this (1e-6) */
+    float rho_tol;         /* |psi|^2 above this at the end sets NONZERO_MIN (1e-10) */
+} vx_refine_params;
+
+/* status bits of a sample */
+#define VX_SAMPLE_MULTI 1u            /* 4 or 6 pierced faces (branch / reconnection cell) */
+#define VX_SAMPLE_TANGENT_FALLBACK 2u /* pseudo-vorticity degenerate; face flux used */
+#define VX_SAMPLE_BOUNDARY 4u         /* a trial point left the patch and was rejected */
+#define VX_SAMPLE_NONZERO_MIN 8u      /* |psi|^2 > rho_tol at the end */
+#define VX_SAMPLE_NOT_CONVERGED 16u   /* Newton ended without a short step, rho > rho_tol */
+#define VX_SAMPLE_NO_FACES 32u        /* the listed cell has no pierced face */
+
+typedef struct {
+    uint64_t cell;    /* cell id */
+    float off[3];     /* sample position relative to the cell's min corner, cells */
+    float rho;        /* |psi|^2 at the sample */
+    uint16_t iters;   /* descent + Newton steps taken */
+    uint16_t status;  /* VX_SAMPLE_* bits */
+    uint32_t reserved;
+} vx_sample; /* 32 bytes */
+
+/* Defaults of vx_refine_params. */
+vx_refine_params vx_refine_defaults(void);
+
+vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                    const uint16_t *d_cell_desc, const float *d_seed_off, const int64_t *d_count,
+                    int64_t cap, const vx_refine_params *p, vx_sample *d_out, vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
+ * Kernel timing with HIP events on the launch stream (measurement support).
+ * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate inference, 3 = batch.
+ * ---------------------------------------------------------------------------------------- */
+vx_status vx_profile_enable(vx_handle *h, int enable); /* enabling clears the accumulators */
+/* Sum of the recorded kernel durations (ms) and their number; synchronises the recorded events. */
+vx_status vx_profile_read(vx_handle *h, int kind, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VX_H */

@@ -1,0 +1,212 @@
+"""Python binding of libvx.so: argument marshalling only.
+
+Every compute step runs in the library's HIP kernels. PyTorch provides device memory and the
+stream; tensors are passed by data pointer. The functions carry the C-ABI names and raise
+``VxError`` when a call returns a non-zero status. There is no CPU fallback: without a built
+``libvx.so`` (and a GPU) the calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvx.so")
+
+_lib = None
+
+VX_OK, VX_ERR_INVALID, VX_ERR_CAPACITY, VX_ERR_DEVICE, VX_ERR_NOMEM, VX_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+SAMPLE_MULTI = 1
+SAMPLE_TANGENT_FALLBACK = 2
+SAMPLE_BOUNDARY = 4
+SAMPLE_NONZERO_MIN = 8
+SAMPLE_NOT_CONVERGED = 16
+SAMPLE_NO_FACES = 32
+
+KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH = 0, 1, 2, 3
+
+# every symbol include/vx.h declares
+EXPORTS = ["vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
+           "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
+           "vx_profile_enable", "vx_profile_read"]
+
+
+class VxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("periodic", ctypes.c_uint32)]
+
+
+class Tangle(ctypes.Structure):
+    _fields_ = [("nwaves", ctypes.c_int32), ("table_size", ctypes.c_uint32), ("d_ax", ctypes.c_void_p),
+                ("d_ay", ctypes.c_void_p), ("d_az", ctypes.c_void_p), ("d_coef", ctypes.c_void_p),
+                ("d_table", ctypes.c_void_p)]
+
+
+class LineRing(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("line_x", "line_y", "ring_cx", "ring_cy", "ring_cz", "radius", "xi")]
+
+
+class WindingOut(ctypes.Structure):
+    _fields_ = [("d_wind", ctypes.c_void_p), ("d_faces", ctypes.c_void_p), ("d_face_sign", ctypes.c_void_p),
+                ("face_cap", ctypes.c_int64), ("d_cells", ctypes.c_void_p), ("d_cell_desc", ctypes.c_void_p),
+                ("cell_cap", ctypes.c_int64), ("d_counts", ctypes.c_void_p)]
+
+
+class RefineParams(ctypes.Structure):
+    _fields_ = [("max_descent", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("max_halvings", ctypes.c_int32), ("step0", ctypes.c_float), ("step_max", ctypes.c_float),
+                ("armijo", ctypes.c_float), ("descent_tol", ctypes.c_float), ("newton_tol", ctypes.c_float),
+                ("rho_tol", ctypes.c_float)]
+
+
+class Sample(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_uint64), ("off", ctypes.c_float * 3), ("rho", ctypes.c_float),
+                ("iters", ctypes.c_uint16), ("status", ctypes.c_uint16), ("reserved", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(Sample) == 32
+
+
+def build():
+    from . import _build
+    return _build.build()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libvx.so (building it first if it has never been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P, i, st = ctypes.c_void_p, ctypes.c_int, ctypes.c_int
+        L.vx_version.restype = i
+        L.vx_create.argtypes = [i, ctypes.POINTER(P)]
+        L.vx_create.restype = st
+        L.vx_destroy.argtypes = [P]
+        L.vx_destroy.restype = st
+        L.vx_status_str.argtypes = [i]
+        L.vx_status_str.restype = ctypes.c_char_p
+        L.vx_last_error.argtypes = [P]
+        L.vx_last_error.restype = ctypes.c_char_p
+        L.vx_gen_tangle.argtypes = [P, Dims, ctypes.POINTER(Tangle), P, P]
+        L.vx_gen_tangle.restype = st
+        L.vx_gen_line_ring.argtypes = [P, Dims, ctypes.POINTER(LineRing), P, P, P]
+        L.vx_gen_line_ring.restype = st
+        L.vx_winding.argtypes = [P, Dims, P, ctypes.POINTER(WindingOut), P]
+        L.vx_winding.restype = st
+        L.vx_wind_config.argtypes = [P, i, i]
+        L.vx_wind_config.restype = st
+        L.vx_refine_defaults.argtypes = []
+        L.vx_refine_defaults.restype = RefineParams
+        L.vx_refine.argtypes = [P, Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
+        L.vx_refine.restype = st
+        L.vx_profile_enable.argtypes = [P, i]
+        L.vx_profile_enable.restype = st
+        L.vx_profile_read.argtypes = [P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.vx_profile_read.restype = st
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------------------------- helpers
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(h, status: int, what: str):
+    if status != VX_OK:
+        L = lib()
+        detail = L.vx_last_error(h).decode() if h else ""
+        raise VxError(status, f"{what}: {L.vx_status_str(status).decode()} {detail}")
+
+
+def dims(nx: int, ny: int, nz: int, periodic: int = 7) -> Dims:
+    return Dims(int(nx), int(ny), int(nz), int(periodic))
+
+
+# ---------------------------------------------------------------------------------------------- C-ABI
+def vx_version() -> int:
+    return lib().vx_version()
+
+
+def vx_create(device: int = 0):
+    h = ctypes.c_void_p()
+    _check(None, lib().vx_create(int(device), ctypes.byref(h)), "vx_create")
+    return h
+
+
+def vx_destroy(h) -> None:
+    _check(None, lib().vx_destroy(h), "vx_destroy")
+
+
+def vx_last_error(h) -> str:
+    return lib().vx_last_error(h).decode()
+
+
+def vx_gen_tangle(h, d: Dims, ax, ay, az, coef, table, psi, stream=None):
+    t = Tangle(int(ax.numel()), int(table.shape[0]), _ptr(ax), _ptr(ay), _ptr(az), _ptr(coef), _ptr(table))
+    _check(h, lib().vx_gen_tangle(h, d, ctypes.byref(t), _ptr(psi), _stream(stream)), "vx_gen_tangle")
+
+
+def vx_gen_line_ring(h, d: Dims, params, noise, psi, stream=None):
+    p = LineRing(*[float(v) for v in params])
+    _check(h, lib().vx_gen_line_ring(h, d, ctypes.byref(p), _ptr(noise), _ptr(psi), _stream(stream)),
+           "vx_gen_line_ring")
+
+
+def vx_winding(h, d: Dims, psi, counts, wind=None, faces=None, fsign=None, cells=None, cdesc=None,
+               stream=None):
+    out = WindingOut(_ptr(wind), _ptr(faces), _ptr(fsign), int(faces.numel()) if faces is not None else 0,
+                     _ptr(cells), _ptr(cdesc), int(cells.numel()) if cells is not None else 0, _ptr(counts))
+    _check(h, lib().vx_winding(h, d, _ptr(psi), ctypes.byref(out), _stream(stream)), "vx_winding")
+
+
+def vx_wind_config(h, rows_per_wave: int = 0, zchunk: int = 0):
+    _check(h, lib().vx_wind_config(h, int(rows_per_wave), int(zchunk)), "vx_wind_config")
+
+
+def vx_refine_defaults() -> RefineParams:
+    return lib().vx_refine_defaults()
+
+
+def vx_refine(h, d: Dims, psi, cells, cdesc, count, out, params: RefineParams | None = None, seed=None,
+              stream=None, cap: int | None = None):
+    cap = int(out.numel() * out.element_size() // 32) if cap is None else int(cap)
+    prm = params if params is not None else vx_refine_defaults()
+    _check(h, lib().vx_refine(h, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(seed), _ptr(count), cap,
+                              ctypes.byref(prm), _ptr(out), _stream(stream)), "vx_refine")
+
+
+def vx_profile_enable(h, enable: bool = True):
+    _check(h, lib().vx_profile_enable(h, int(bool(enable))), "vx_profile_enable")
+
+
+def vx_profile_read(h, kind: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(h, lib().vx_profile_read(h, int(kind), ctypes.byref(ms), ctypes.byref(n)), "vx_profile_read")
+    return ms.value, n.value
+
+
+from .pipeline import Extractor, upload_tangle, samples_to_numpy  # noqa: E402,F401

@@ -1,0 +1,211 @@
+// Handle, error state, validation, event timing and the C-ABI entry points of libvx.so.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "vx_internal.h"
+
+extern "C" int vx_version(void) { return 10000; }
+
+extern "C" const char *vx_status_str(int st) {
+    switch (st) {
+        case VX_OK: return "VX_OK";
+        case VX_ERR_INVALID: return "VX_ERR_INVALID";
+        case VX_ERR_CAPACITY: return "VX_ERR_CAPACITY";
+        case VX_ERR_DEVICE: return "VX_ERR_DEVICE";
+        case VX_ERR_NOMEM: return "VX_ERR_NOMEM";
+        case VX_ERR_UNSUPPORTED: return "VX_ERR_UNSUPPORTED";
+        default: return "VX_ERR_UNKNOWN";
+    }
+}
+
+vx_status vx_fail(vx_handle *h, vx_status st, const char *fmt, ...) {
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->err = buf;
+    }
+    return st;
+}
+
+vx_status vx_hip_check(vx_handle *h, hipError_t e, const char *what) {
+    if (e == hipSuccess) return VX_OK;
+    return vx_fail(h, e == hipErrorOutOfMemory ? VX_ERR_NOMEM : VX_ERR_DEVICE, "%s: %s", what,
+                   hipGetErrorString(e));
+}
+
+vx_status vx_bind(vx_handle *h) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device)
+        return vx_hip_check(h, hipSetDevice(h->device), "hipSetDevice");
+    return VX_OK;
+}
+
+extern "C" vx_status vx_create(int device, vx_handle **out) {
+    if (!out) return VX_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return VX_ERR_INVALID;
+    vx_handle *h = new (std::nothrow) vx_handle();
+    if (!h) return VX_ERR_NOMEM;
+    h->device = device;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete h;
+        return VX_ERR_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete h;
+        return VX_ERR_DEVICE;
+    }
+    h->num_cu = prop.multiProcessorCount;
+    *out = h;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_destroy(vx_handle *h) {
+    if (!h) return VX_OK;
+    (void)hipSetDevice(h->device);
+    for (auto &p : h->events) {
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
+    }
+    delete h;
+    return VX_OK;
+}
+
+extern "C" const char *vx_last_error(const vx_handle *h) { return h ? h->err.c_str() : ""; }
+
+// ------------------------------------------------------------------------------- timing
+vx_timer::vx_timer(vx_handle *h_, hipStream_t s_, int kind_) : h(h_), s(s_), kind(kind_) {
+    if (!h->profile) return;
+    if (h->events_used == h->events.size()) {
+        vx_event_pair p{};
+        if (hipEventCreate(&p.start) != hipSuccess) return;
+        if (hipEventCreate(&p.stop) != hipSuccess) {
+            (void)hipEventDestroy(p.start);
+            return;
+        }
+        h->events.push_back(p);
+    }
+    pair = &h->events[h->events_used++];
+    pair->kind = kind;
+    (void)hipEventRecord(pair->start, s);
+}
+
+void vx_timer::stop() {
+    if (pair) (void)hipEventRecord(pair->stop, s);
+    pair = nullptr;
+}
+
+extern "C" vx_status vx_profile_enable(vx_handle *h, int enable) {
+    if (!h) return VX_ERR_INVALID;
+    h->profile = enable != 0;
+    h->events_used = 0;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_profile_read(vx_handle *h, int kind, double *total_ms, int64_t *launches) {
+    if (!h || !total_ms || !launches || kind < 0 || kind >= VX_KIND_COUNT)
+        return vx_fail(h, VX_ERR_INVALID, "vx_profile_read: bad arguments");
+    vx_status st = vx_bind(h);
+    if (st) return st;
+    double sum = 0.0;
+    int64_t n = 0;
+    for (size_t i = 0; i < h->events_used; ++i) {
+        auto &p = h->events[i];
+        if (p.kind != kind) continue;
+        st = vx_hip_check(h, hipEventSynchronize(p.stop), "hipEventSynchronize");
+        if (st) return st;
+        float ms = 0.f;
+        st = vx_hip_check(h, hipEventElapsedTime(&ms, p.start, p.stop), "hipEventElapsedTime");
+        if (st) return st;
+        sum += ms;
+        ++n;
+    }
+    *total_ms = sum;
+    *launches = n;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk) {
+    if (!h) return VX_ERR_INVALID;
+    if (rows_per_wave != 0 && rows_per_wave != 1 && rows_per_wave != 2 && rows_per_wave != 4)
+        return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: rows_per_wave must be 0, 1, 2 or 4");
+    if (zchunk < 0) return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: negative zchunk");
+    h->wind_ty = rows_per_wave;
+    h->wind_zc = zchunk;
+    return VX_OK;
+}
+
+// ------------------------------------------------------------------------------- validation
+vx_status vx_check_dims(vx_handle *h, const vx_dims &d) {
+    const int32_t n[3] = {d.nx, d.ny, d.nz};
+    if (d.periodic > 7u) return vx_fail(h, VX_ERR_INVALID, "periodic mask 0x%x has bits above 2", d.periodic);
+    for (int a = 0; a < 3; ++a) {
+        bool per = (d.periodic >> a) & 1u;
+        if (n[a] < (per ? 2 : 1))
+            return vx_fail(h, VX_ERR_INVALID, "dims[%d] = %d must be >= %d", a, n[a], per ? 2 : 1);
+    }
+    const double nodes = (double)d.nx * d.ny * d.nz;
+    if (nodes * 3.0 >= 18446744073709551615.0)
+        return vx_fail(h, VX_ERR_UNSUPPORTED, "grid too large for 64-bit face ids");
+    return VX_OK;
+}
+
+// ------------------------------------------------------------------------------- entry points
+extern "C" vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_winding_out *out,
+                                vx_stream s) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (!d_psi || !out) return vx_fail(h, VX_ERR_INVALID, "vx_winding: null psi or out");
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (((uintptr_t)d_psi & 15u) != 0) return vx_fail(h, VX_ERR_INVALID, "psi must be 16-byte aligned");
+    if (!out->d_counts) return vx_fail(h, VX_ERR_INVALID, "vx_winding: d_counts is required");
+    if (((uintptr_t)out->d_wind & 3u) != 0) return vx_fail(h, VX_ERR_INVALID, "d_wind must be 4-byte aligned");
+    if (((uintptr_t)out->d_counts & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "d_counts must be 8-byte aligned");
+    if (out->face_cap < 0 || out->cell_cap < 0) return vx_fail(h, VX_ERR_INVALID, "negative capacity");
+    if (out->face_cap > 0 && (!out->d_faces || !out->d_face_sign))
+        return vx_fail(h, VX_ERR_INVALID, "face_cap > 0 needs d_faces and d_face_sign");
+    if (out->cell_cap > 0 && (!out->d_cells || !out->d_cell_desc))
+        return vx_fail(h, VX_ERR_INVALID, "cell_cap > 0 needs d_cells and d_cell_desc");
+    if (vx_status st = vx_bind(h)) return st;
+    return vx_wind_launch(h, dims, d_psi, *out, (hipStream_t)s);
+}
+
+extern "C" vx_refine_params vx_refine_defaults(void) {
+    vx_refine_params p;
+    p.max_descent = 32;
+    p.max_newton = 20;
+    p.max_halvings = 30;
+    p.step0 = 0.25f;
+    p.step_max = 1.0f;
+    p.armijo = 1e-4f;
+    p.descent_tol = 1e-2f;
+    p.newton_tol = 1e-6f;
+    p.rho_tol = 1e-10f;
+    return p;
+}
+
+extern "C" vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                               const uint16_t *d_cell_desc, const float *d_seed_off,
+                               const int64_t *d_count, int64_t cap, const vx_refine_params *p,
+                               vx_sample *d_out, vx_stream s) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (cap < 0) return vx_fail(h, VX_ERR_INVALID, "vx_refine: negative capacity");
+    if (cap == 0) return VX_OK;
+    if (!d_psi || !d_cells || !d_cell_desc || !d_count || !d_out)
+        return vx_fail(h, VX_ERR_INVALID, "vx_refine: null pointer argument");
+    vx_refine_params prm = p ? *p : vx_refine_defaults();
+    if (prm.max_descent < 0 || prm.max_newton < 0 || prm.max_halvings < 0 || prm.max_descent > 100000 ||
+        prm.max_newton > 100000 || prm.max_halvings > 200 || !(prm.step0 > 0.f) || !(prm.step_max > 0.f))
+        return vx_fail(h, VX_ERR_INVALID, "vx_refine: bad parameters");
+    if (vx_status st = vx_bind(h)) return st;
+    return vx_refine_launch(h, dims, d_psi, d_cells, d_cell_desc, d_seed_off, d_count, cap, prm, d_out,
+                            (hipStream_t)s);
+}

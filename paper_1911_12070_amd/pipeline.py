@@ -1,0 +1,118 @@
+"""Convenience layer over the C-ABI: allocates caller-owned buffers with torch and chains the calls.
+
+Nothing here computes on the data: it only sizes buffers, moves pointers and copies results to
+the host for inspection.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (dims as make_dims, vx_create, vx_destroy, vx_gen_line_ring, vx_gen_tangle, vx_refine,
+               vx_refine_defaults, vx_winding, vx_wind_config)
+
+SAMPLE_DTYPE = np.dtype([("cell", "<u8"), ("off", "<f4", (3,)), ("rho", "<f4"), ("iters", "<u2"),
+                         ("status", "<u2"), ("reserved", "<u4")])
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libvx needs a ROCm GPU; none is visible")
+    return torch
+
+
+def upload_tangle(tangle, device="cuda"):
+    """Device copies of a tangle's integer phase steps, coefficients and phase table."""
+    torch = _torch()
+    ax, ay, az = tangle.phase_steps()
+    to = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+    return dict(ax=to(ax.astype(np.int32), torch.int32), ay=to(ay.astype(np.int32), torch.int32),
+                az=to(az.astype(np.int32), torch.int32), coef=to(tangle.coef_pairs(), torch.float64),
+                table=to(tangle.table(), torch.float64))
+
+
+def samples_to_numpy(t, n: int | None = None) -> np.ndarray:
+    a = t.detach().cpu().numpy().view(np.uint8).reshape(-1)
+    s = a.view(SAMPLE_DTYPE)
+    return s if n is None else s[:n]
+
+
+class Extractor:
+    """One handle plus torch-allocated output buffers."""
+
+    def __init__(self, device: int = 0):
+        self.torch = _torch()
+        self.device = device
+        self.h = vx_create(device)
+
+    def close(self):
+        if self.h is not None:
+            vx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def config(self, rows_per_wave: int = 0, zchunk: int = 0):
+        vx_wind_config(self.h, rows_per_wave, zchunk)
+
+    # ------------------------------------------------------------------ inputs
+    def gen_tangle(self, tangle, stream=None):
+        torch = self.torch
+        nx, ny, nz = tangle.dims
+        prm = upload_tangle(tangle, f"cuda:{self.device}")
+        psi = torch.empty((nz, ny, nx), dtype=torch.complex64, device=f"cuda:{self.device}")
+        vx_gen_tangle(self.h, make_dims(nx, ny, nz), prm["ax"], prm["ay"], prm["az"], prm["coef"],
+                      prm["table"], psi, stream)
+        return psi
+
+    def gen_line_ring(self, lr, stream=None):
+        torch = self.torch
+        nx, ny, nz = lr.dims
+        noise = lr.noise()
+        d_noise = torch.from_numpy(noise).to(f"cuda:{self.device}") if noise is not None else None
+        psi = torch.empty((nz, ny, nx), dtype=torch.complex64, device=f"cuda:{self.device}")
+        prm = [*lr.line, *lr.ring_center, lr.radius, lr.xi]
+        vx_gen_line_ring(self.h, make_dims(nx, ny, nz), prm, d_noise, psi, stream)
+        return psi
+
+    # ------------------------------------------------------------------ outputs
+    def alloc_winding(self, shape, face_cap: int | None = None, cell_cap: int | None = None,
+                      wind: bool = True):
+        torch = self.torch
+        nz, ny, nx = shape
+        n = nx * ny * nz
+        # a tangle pierces a few per cent of faces at most; dense small test fields need more room
+        face_cap = max(4096, n // 4) if face_cap is None else face_cap
+        cell_cap = max(4096, n // 4) if cell_cap is None else cell_cap
+        dev = f"cuda:{self.device}"
+        return dict(
+            wind=torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev) if wind else None,
+            faces=torch.empty(face_cap, dtype=torch.int64, device=dev),
+            fsign=torch.empty(face_cap, dtype=torch.int8, device=dev),
+            cells=torch.empty(cell_cap, dtype=torch.int64, device=dev),
+            cdesc=torch.empty(cell_cap, dtype=torch.int16, device=dev),
+            counts=torch.zeros(2, dtype=torch.int64, device=dev),
+        )
+
+    def winding(self, psi, periodic: int = 7, out=None, stream=None):
+        nz, ny, nx = psi.shape
+        out = out or self.alloc_winding(psi.shape)
+        vx_winding(self.h, make_dims(nx, ny, nz, periodic), psi, out["counts"], out["wind"], out["faces"],
+                   out["fsign"], out["cells"], out["cdesc"], stream)
+        return out
+
+    def alloc_samples(self, cap: int):
+        return self.torch.empty((cap, 8), dtype=self.torch.int32, device=f"cuda:{self.device}")
+
+    def refine(self, psi, wout, periodic: int = 7, samples=None, params=None, seed=None, stream=None):
+        nz, ny, nx = psi.shape
+        cap = wout["cells"].numel()
+        samples = samples if samples is not None else self.alloc_samples(cap)
+        vx_refine(self.h, make_dims(nx, ny, nz, periodic), psi, wout["cells"], wout["cdesc"],
+                  wout["counts"][1:], samples, params or vx_refine_defaults(), seed, stream,
+                  cap=min(cap, samples.shape[0]))
+        return samples
