@@ -16,7 +16,7 @@
  * Conventions
  *   Grid       node (i,j,k), 0 <= i < nx etc., linear id n = i + nx*(j + ny*k) (x fastest).
  *   psi        complex64, interleaved (re, im), nx*ny*nz values in node order, device memory,
- *              16-byte aligned. Values must be finite.
+ *              8-byte aligned. Values must be finite.
  *   Periodic   bit a of vx_dims.periodic makes axis a periodic (index nx wraps to 0). On a
  *              non-periodic axis the faces and cells that would need index n_a do not exist:
  *              their windings are 0 and they are never listed.
@@ -137,9 +137,8 @@ typedef struct {
 vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_winding_out *out,
                      vx_stream s);
 
-/* Tile shape of the winding kernel on this handle: rows_per_wave in {1, 2, 4} (0 = default 1),
- * zchunk = planes marched per workgroup (0 = chosen from the grid size). Results do not depend on
- * it. nx must be a multiple of 4 for vx_winding (VX_ERR_UNSUPPORTED otherwise). */
+/* Tile shape of the winding kernel on this handle: zchunk = planes marched per wavefront (0 = chosen
+ * from the grid size); rows_per_wave is reserved and must be 0. Results do not depend on it. */
 vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk);
 
 /* ------------------------------------------------------------------------------------------

@@ -133,8 +133,7 @@ extern "C" vx_status vx_profile_read(vx_handle *h, int kind, double *total_ms, i
 
 extern "C" vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk) {
     if (!h) return VX_ERR_INVALID;
-    if (rows_per_wave != 0 && rows_per_wave != 1 && rows_per_wave != 2 && rows_per_wave != 4)
-        return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: rows_per_wave must be 0, 1, 2 or 4");
+    if (rows_per_wave != 0) return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: rows_per_wave must be 0");
     if (zchunk < 0) return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: negative zchunk");
     h->wind_ty = rows_per_wave;
     h->wind_zc = zchunk;
@@ -163,9 +162,8 @@ extern "C" vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, c
     h->err.clear();
     if (!d_psi || !out) return vx_fail(h, VX_ERR_INVALID, "vx_winding: null psi or out");
     if (vx_status st = vx_check_dims(h, dims)) return st;
-    if (((uintptr_t)d_psi & 15u) != 0) return vx_fail(h, VX_ERR_INVALID, "psi must be 16-byte aligned");
+    if (((uintptr_t)d_psi & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "psi must be 8-byte aligned");
     if (!out->d_counts) return vx_fail(h, VX_ERR_INVALID, "vx_winding: d_counts is required");
-    if (((uintptr_t)out->d_wind & 3u) != 0) return vx_fail(h, VX_ERR_INVALID, "d_wind must be 4-byte aligned");
     if (((uintptr_t)out->d_counts & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "d_counts must be 8-byte aligned");
     if (out->face_cap < 0 || out->cell_cap < 0) return vx_fail(h, VX_ERR_INVALID, "negative capacity");
     if (out->face_cap > 0 && (!out->d_faces || !out->d_face_sign))

@@ -70,6 +70,12 @@ CASES = [
     ((40, 33, 17), 4, "tangle", 11),
     ((40, 33, 17), 6, "int", 12),
     ((8, 8, 1), 3, "tangle", 13),        # single plane, z not periodic (a 2D field)
+    ((37, 29, 13), 7, "tangle", 14),     # odd sizes, one tile with wrapped halo column and row
+    ((127, 63, 5), 7, "tangle", 15),     # 63/31 tile boundaries: 3 x-tiles, 3 y-tiles
+    ((126, 62, 4), 5, "tangle", 16),     # exact multiples of the tile outputs, y not periodic
+    ((1, 5, 3), 6, "int", 17),           # one column, x not periodic
+    ((2, 2, 2), 7, "int", 18),
+    ((64, 32, 8), 3, "int", 19),
 ]
 
 
@@ -85,7 +91,7 @@ def _field(dims, kind, seed):
 
 
 @pytest.mark.parametrize("dims,periodic,kind,seed", CASES)
-@pytest.mark.parametrize("ty,zc", [(1, 0), (2, 3), (4, 0), (1, 1)])
+@pytest.mark.parametrize("ty,zc", [(0, 0), (0, 3), (0, 1)])
 def test_winding_parity(ex, dims, periodic, kind, seed, ty, zc):
     log(f"winding {dims} periodic={periodic} {kind} ty={ty} zc={zc}")
     psi = _field(dims, kind, seed)
@@ -134,8 +140,10 @@ def test_invalid_arguments_are_rejected(ex):
     from paper_1911_12070_amd import VxError, dims, vx_winding
     psi = torch.zeros((4, 4, 6), dtype=torch.complex64, device="cuda:0")
     counts = torch.zeros(2, dtype=torch.int64, device="cuda:0")
-    with pytest.raises(VxError):   # nx not a multiple of 4
-        vx_winding(ex.h, dims(6, 4, 4), psi, counts)
+    with pytest.raises(VxError):   # bits above the three axes in the periodic mask
+        vx_winding(ex.h, dims(6, 4, 4, 8), psi, counts)
+    with pytest.raises(VxError):   # misaligned psi
+        vx_winding(ex.h, dims(6, 4, 4), psi.data_ptr() + 4, counts)
     with pytest.raises(VxError):   # periodic axis of size 1
         vx_winding(ex.h, dims(4, 4, 1, 7), psi, counts)
     with pytest.raises(VxError):   # no counts buffer
