@@ -3,30 +3,41 @@
 // graph in dual form), in one pass over psi.
 //
 // Bit-sliced formulation
-//   A wavefront owns a tile of 64 x-columns (one per lane) by 32 rows and marches along z over a
-//   chunk of planes. For each plane a lane packs, for its column, one bit per row into 32-bit words:
-//   "Im psi > 0" and "Re psi < 0". Everything after that is bitwise logic on words, 32 nodes at a time:
+//   A wavefront owns a tile of 16 rows by 128 x-columns and marches along z over a chunk of planes.
+//   Lane (r, c) = (lane / 4, lane % 4) holds row r, columns 32c .. 32c+31 of the tile. For each plane
+//   a lane packs, for its 32 nodes, one bit per node into 32-bit words: "Im psi > 0" and
+//   "Re psi < 0". Everything after that is bitwise logic on words, 32 nodes at a time:
 //     * an edge a->b crosses Im = 0 where the Im bits differ (upwards if b's bit is set);
 //     * if Re a and Re b are both >= 0 the crossing counts (+1 up, -1 down); if both are < 0 it does
 //       not; only when Re also changes sign is the determinant Re a Im b - Im a Re b needed, and it is
 //       formed from the FP32 values in FP64 (both products exact), for those few edges only;
 //     * the winding of a face is the sum of four edge terms in {-1,0,1}; with |w| <= 1 it is nonzero
 //       iff an odd number of terms are nonzero, and +1 iff some term is +1 and fewer than two are -1;
-//     * neighbours: x+1 is the next lane (cross-lane move of a whole word), y+1 is the next bit,
-//       z+1 is the next plane of the march.
-//   Lane 63 and row 31 are halo: a tile outputs 63 columns x 31 rows, so every neighbour an output
-//   needs lies inside the tile; neighbouring tiles overlap by one column and one row (re-read from
-//   L2). The first plane of a chunk is the z halo of the previous chunk.
-//   Pierced faces and cells are appended per wavefront into LDS (ballot + mbcnt) and flushed with one
-//   global atomic per list when the buffer fills. Workgroups are renumbered so that each XCD gets a
-//   contiguous range of tiles, keeping halo re-reads inside one XCD's L2.
+//     * neighbours: x+1 is the next bit (the word's last bit takes bit 0 of the next lane of the quad),
+//       y+1 is four lanes on, z+1 is the next plane of the march.
+//   Row 15 (lanes 60-63) is halo: a tile outputs 15 rows; neighbouring tiles overlap by one row.
+//   Column 128 is halo too: the quad's last lane keeps it as one extra bit and forms only the
+//   quantities the tile's last column needs from it. The first plane of a chunk is the z halo of the
+//   previous chunk.
+//
+// Memory
+//   psi for the next plane is requested a whole march step ahead with direct global->LDS loads:
+//   each instruction fetches one full 1 KiB row of the tile. Inside LDS each row's 16-byte pieces are
+//   rotated per row and chunk so that the per-lane reads that follow spread over all banks. Exact
+//   determinants read their operands from LDS (or, for the previous plane, from L2). The packed byte
+//   field of a tile row is one whole 128-byte line written by the row's four lanes, so the writes
+//   reach memory as full lines. Pierced faces and cells are appended per wavefront into LDS
+//   (ballot + mbcnt) and flushed with one global atomic per list when the buffer fills. Workgroups
+//   are renumbered so that each XCD gets a contiguous range of tiles, keeping halo re-reads inside
+//   one XCD's L2.
 #include "vx_internal.h"
 
 namespace {
 
-constexpr int TXO = 63;   // output columns per tile (64 loaded)
-constexpr int TYO = 31;   // output rows per tile (32 loaded)
-constexpr int LBUF = 512; // LDS list entries per wavefront and list
+constexpr int TXO = 128;   // output columns per tile (plus one halo column)
+constexpr int TYO = 15;    // output rows per tile (16 loaded)
+constexpr int LBUF = 256;  // LDS list entries per list
+constexpr int PLANE_LDS = 16 * 1024;  // bytes of one plane tile in LDS (halo column follows)
 
 struct WindArgs {
     const float2 *psi;
@@ -41,6 +52,9 @@ struct WindArgs {
     int nx, ny, nz;
     int px, py, pz;
     int ntx, nty, ntz, zc;
+    int psi_a16;   // psi is 16-byte aligned (16-byte loads allowed)
+    int wind_a16;  // packed field 16-byte aligned
+    int wind_a4;   // packed field 4-byte aligned
 };
 
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
@@ -49,9 +63,18 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return xcd * per + min(xcd, rem) + slot;
 }
 
-// word of lane+1 (lane 63 receives 0; it is a halo lane whose neighbour is never used)
-__device__ __forceinline__ uint32_t next_lane(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xf, 0xf, true);
+// Cross-lane moves read other lanes' registers, which only works while those lanes are active. The
+// empty volatile asm pins each move where it is written (outside any divergent branch), so the
+// compiler cannot sink it into a branch whose exec mask would hide the source lane.
+__device__ __forceinline__ uint32_t pin(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+// word of the next row (lane + 4); the halo row's lanes get their own word, which is never used
+__device__ __forceinline__ uint32_t next_lane(uint32_t v) { return pin((uint32_t)__shfl_down((int)v, 4)); }
+// word of the next lane of the quad (lane + 1 within each group of four; the last keeps its own)
+__device__ __forceinline__ uint32_t quad_next(uint32_t v) {
+    return pin((uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xF9 /* quad_perm:[1,2,3,3] */, 0xf, 0xf, false));
 }
 
 struct WT {  // a ternary value per bit: +1 where p is set, -1 where n is set
@@ -69,9 +92,17 @@ __device__ __forceinline__ WT sum4(WT t1, WT t2, WT t3, WT t4) {
     return WT{wp, nz & ~wp};
 }
 
-__device__ __forceinline__ WT shr1(WT a) { return WT{a.p >> 1, a.n >> 1}; }
 __device__ __forceinline__ WT lane_next(WT a) { return WT{next_lane(a.p), next_lane(a.n)}; }
 __device__ __forceinline__ WT mask(WT a, uint32_t m) { return WT{a.p & m, a.n & m}; }
+// word of column+1: shift down one column; bit 31 takes bit 0 of the quad's next lane, or, in the
+// quad's last lane (m4 all ones), the halo column's bit h
+__device__ __forceinline__ uint32_t colnext(uint32_t w, uint32_t h, uint32_t m4) {
+    const uint32_t nb = (quad_next(w) & ~m4) | (h & m4);
+    return (w >> 1) | (nb << 31);
+}
+__device__ __forceinline__ WT colnext(WT w, WT h, uint32_t m4) {
+    return WT{colnext(w.p, h.p, m4), colnext(w.n, h.n, m4)};
+}
 
 // edge values from the sign words of the two end points; `ex` holds, for edges where both Re and Im
 // change sign, whether the exact determinant test says the crossing counts
@@ -85,13 +116,25 @@ __device__ __forceinline__ uint32_t needs_exact(uint32_t pia, uint32_t pib, uint
     return (pia ^ pib) & (nra ^ nrb);
 }
 
-// exact count decision of the edge a->b (called only when Im and Re both change sign along it)
+// exact count decision of the edge a->b (used only when Im and Re both change sign along it)
 __device__ __forceinline__ bool exact_count(float2 a, float2 b) {
     const double d = fma((double)a.x, (double)b.y, -((double)a.y * (double)b.x));
     return b.y > 0.0f ? (d >= 0.0) : (d <= 0.0);
 }
 
+// LDS byte offset of the 16-byte piece q (columns 2q, 2q+1) of tile row r: inside the row's 1 KiB,
+// chunk q/16 keeps its 16 pieces rotated by r + 4 (q/16), so lanes that read piece i of their own
+// (row, chunk) at the same time spread over all banks.
+__device__ __forceinline__ uint32_t piece_off(int r, int q) {
+    const int cc = q >> 4;
+    return (uint32_t)(r * 1024 + (cc * 16 + ((q + r + 4 * cc) & 15)) * 16);
+}
+
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
+    __shared__ __attribute__((aligned(16))) uint8_t s_plane[PLANE_LDS + 512];
     __shared__ uint64_t s_fbuf[LBUF];
     __shared__ uint64_t s_cbuf[LBUF];
 
@@ -105,85 +148,151 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
     const int x0 = tx * TXO, y0 = ty * TYO, z0 = tz * A.zc;
     const int z1 = min(z0 + A.zc, nz);
 
-    // this lane's column and its +x neighbour's column (load indices, wrapped or clamped)
-    const int xg = x0 + lane;
-    const int xc = xg < nx ? xg : (A.px ? xg % nx : nx - 1);
-    const int xg1 = xg + 1;
-    const int xc1 = xg1 < nx ? xg1 : (A.px ? xg1 % nx : nx - 1);
-    const bool lane_out = lane < TXO && xg < nx;
-    const bool xstep = A.px || (xg + 1 < nx);
+    // this lane's row and column chunk
+    const int r = lane >> 2, c = lane & 3;
+    const bool last4 = c == 3;
+    // lane masks kept opaque to the compiler (see pin): quad's last lane, rows with a row below
+    const uint32_t m4 = pin(last4 ? 0xffffffffu : 0u);
+    const uint32_t minner = pin(r < 15 ? 0xffffffffu : 0u);
+    const int yg = y0 + r;
+    const int yl = yg < ny ? yg : (A.py ? yg % ny : ny - 1);
+    const bool row_out = r < TYO && yg < ny;
+    const bool ystep = A.py || (yg + 1 < ny);
+    // columns of this lane: valid outputs and +x steps; the halo column's load index
+    const int xl0 = x0 + 32 * c;
+    const int ncol = max(0, min(32, nx - xl0));
+    const uint32_t cvalid = ncol >= 32 ? 0xffffffffu : ((1u << ncol) - 1u);
+    uint32_t xstep = cvalid;
+    if (!A.px && ncol > 0 && xl0 + ncol == nx) xstep &= ~(1u << (ncol - 1));
+    const int xh = x0 + TXO < nx ? x0 + TXO : (A.px ? (x0 + TXO) % nx : nx - 1);
+    // interior tiles use 16-byte loads of whole rows; others (ragged last column tile, odd nx) load
+    // per node
+    const bool fast = A.psi_a16 && (x0 + TXO <= nx) && ((nx & 1) == 0);
 
-    // row words: valid output rows and rows whose +y step exists
-    uint32_t rvalid = 0, ystep = 0;
-    for (int r = 0; r < 32; ++r) {
-        const int y = y0 + r;
-        if (r < TYO && y < ny) rvalid |= 1u << r;
-        if (A.py || y + 1 < ny) ystep |= 1u << r;
-    }
-    const bool wrap_rows = y0 + 32 > ny;
+    const float2 *psi = A.psi;
+    const uint64_t plane_nodes = (uint64_t)nx * (uint64_t)ny;
+    auto plane_of = [&](int k) -> int { return k < nz ? k : (A.pz ? k % nz : nz - 1); };
     auto row_of = [&](int r) -> int {
         const int y = y0 + r;
         return y < ny ? y : (A.py ? y % ny : ny - 1);
     };
-    auto plane_of = [&](int k) -> int { return k < nz ? k : (A.pz ? k % nz : nz - 1); };
+    auto col_of = [&](int x) -> int { return x < nx ? x : (A.px ? x % nx : nx - 1); };
 
-    const float2 *psi = A.psi;
-    float2 raw[32];
+    // request plane k of the tile into LDS
     auto issue = [&](int k) {
-        const int64_t pbase = (int64_t)plane_of(k) * ny;
-        if (!wrap_rows) {
-            const float2 *p = psi + (pbase + y0) * nx + xc;
+        const float2 *pl = psi + (uint64_t)plane_of(k) * plane_nodes;
+        if (fast) {
+            const int cc = lane >> 4, xx = lane & 15;
 #pragma unroll
-            for (int r = 0; r < 32; ++r) raw[r] = p[(int64_t)r * nx];
+            for (int j = 0; j < 16; ++j) {
+                // row j: lane L lands at slot L; it fetches the piece whose rotated slot is L
+                const int q = 16 * cc + ((xx - j - 4 * cc) & 15);
+                const float2 *src = pl + (uint64_t)row_of(j) * nx + x0 + 2 * q;
+                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                                 (void __attribute__((address_space(3))) *)(s_plane + j * 1024),
+                                                 16, 0, 0);
+            }
         } else {
-#pragma unroll
-            for (int r = 0; r < 32; ++r) raw[r] = psi[(pbase + row_of(r)) * nx + xc];
+            const float2 *rowp = pl + (uint64_t)yl * nx;
+#pragma unroll 4
+            for (int i = 0; i < 16; ++i) {
+                const int q = 16 * c + i;
+                const float2 a = rowp[col_of(x0 + 2 * q)], b = rowp[col_of(x0 + 2 * q + 1)];
+                *reinterpret_cast<float4 *>(s_plane + piece_off(r, q)) = make_float4(a.x, a.y, b.x, b.y);
+            }
         }
+        // halo column of each row: Re and Im land in two 256-byte arrays (4 bytes per lane each)
+        const float *hsrc = reinterpret_cast<const float *>(pl + (uint64_t)yl * nx + xh);
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)hsrc,
+                                         (void __attribute__((address_space(3))) *)(s_plane + PLANE_LDS), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(hsrc + 1),
+                                         (void __attribute__((address_space(3))) *)(s_plane + PLANE_LDS + 256), 4, 0, 0);
     };
-    auto sign_words = [&](uint32_t &pi, uint32_t &nr) {
+    auto lds_node = [&](int rr, int col) -> float2 {  // tile row, tile column (128 = halo column)
+        if (col == TXO)
+            return make_float2(*reinterpret_cast<const float *>(s_plane + PLANE_LDS + (4 * rr + 3) * 4),
+                               *reinterpret_cast<const float *>(s_plane + PLANE_LDS + 256 + (4 * rr + 3) * 4));
+        return *reinterpret_cast<const float2 *>(s_plane + piece_off(rr, col >> 1) + (col & 1) * 8);
+    };
+    // sign words of this lane's row from the plane in LDS
+    auto sign_words = [&](uint32_t &pi, uint32_t &nr, uint32_t &pih, uint32_t &nrh) {
         uint32_t a = 0, b = 0;
 #pragma unroll
-        for (int r = 0; r < 32; ++r) {
-            a |= raw[r].y > 0.0f ? (1u << r) : 0u;
-            b |= raw[r].x < 0.0f ? (1u << r) : 0u;
+        for (int i = 0; i < 16; ++i) {
+            const float4 v = *reinterpret_cast<const float4 *>(s_plane + piece_off(r, 16 * c + i));
+            a |= (v.y > 0.0f ? 1u : 0u) << (2 * i);
+            a |= (v.w > 0.0f ? 1u : 0u) << (2 * i + 1);
+            b |= (v.x < 0.0f ? 1u : 0u) << (2 * i);
+            b |= (v.z < 0.0f ? 1u : 0u) << (2 * i + 1);
         }
+        const float2 h = make_float2(*reinterpret_cast<const float *>(s_plane + PLANE_LDS + lane * 4),
+                                     *reinterpret_cast<const float *>(s_plane + PLANE_LDS + 256 + lane * 4));
         pi = a;
         nr = b;
-    };
-    auto node_ptr = [&](int col, int r, int k) -> const float2 * {
-        return psi + ((int64_t)plane_of(k) * ny + row_of(r)) * nx + col;
+        pih = h.y > 0.0f ? 1u : 0u;
+        nrh = h.x < 0.0f ? 1u : 0u;
     };
 
-    // Resolve the pending exact edges of the in-plane (x, y) edges of plane k and, if qz is given,
-    // of the z edges k -> k+1. Returns the count-decision words.
-    auto resolve = [&](uint32_t qx, uint32_t qy, uint32_t qz, int k, uint32_t &ex, uint32_t &ey, uint32_t &ez) {
-        ex = ey = ez = 0;
-        while (__ballot((qx | qy | qz) != 0u) != 0) {
-            if ((qx | qy | qz) != 0u) {
-                int dir, r;
+    // Exact decisions for the pending edges of the plane in LDS (x: bit b -> b+1, y: row r -> r+1)
+    // and of the z edges from plane kprev (read from L2) to the plane in LDS. Bit 0 of hy/hz: the halo
+    // column (quad's last lane only).
+    auto resolve = [&](uint32_t qx, uint32_t qy, uint32_t qz, uint32_t hy, uint32_t hz, int kprev,
+                       uint32_t &ex, uint32_t &ey, uint32_t &ez, uint32_t &ehy, uint32_t &ehz) {
+        ex = ey = ez = ehy = ehz = 0;
+        const float2 *prev = psi + (uint64_t)plane_of(kprev) * plane_nodes + (uint64_t)yl * nx;
+        while (__ballot((qx | qy | qz | hy | hz) != 0u) != 0) {
+            if ((qx | qy | qz | hy | hz) != 0u) {
+                int dir, b;
                 if (qx) {
                     dir = 0;
-                    r = __builtin_ctz(qx);
+                    b = __builtin_ctz(qx);
                 } else if (qy) {
                     dir = 1;
-                    r = __builtin_ctz(qy);
+                    b = __builtin_ctz(qy);
+                } else if (qz) {
+                    dir = 2;
+                    b = __builtin_ctz(qz);
+                } else if (hy) {
+                    dir = 1;
+                    b = 32;
                 } else {
                     dir = 2;
-                    r = __builtin_ctz(qz);
+                    b = 32;
                 }
-                const float2 a = *node_ptr(xc, r, dir == 2 ? k - 1 : k);
-                const float2 b = dir == 0 ? *node_ptr(xc1, r, k) : (dir == 1 ? *node_ptr(xc, r + 1, k) : *node_ptr(xc, r, k));
-                const uint32_t bit = 1u << r;
-                const uint32_t c = exact_count(a, b) ? bit : 0u;
+                const int col = b == 32 ? TXO : 32 * c + b;  // tile column
+                float2 a, v;
                 if (dir == 0) {
-                    ex |= c;
-                    qx &= ~bit;
+                    a = lds_node(r, col);
+                    v = lds_node(r, col + 1);
                 } else if (dir == 1) {
-                    ey |= c;
-                    qy &= ~bit;
+                    a = lds_node(r, col);
+                    v = lds_node(r + 1, col);
                 } else {
-                    ez |= c;
-                    qz &= ~bit;
+                    a = prev[col == TXO ? xh : col_of(x0 + col)];
+                    v = lds_node(r, col);
+                }
+                const bool cnt = exact_count(a, v);
+                if (b == 32) {
+                    if (dir == 1) {
+                        ehy = cnt ? 1u : 0u;
+                        hy = 0;
+                    } else {
+                        ehz = cnt ? 1u : 0u;
+                        hz = 0;
+                    }
+                } else {
+                    const uint32_t bit = 1u << b;
+                    const uint32_t m = cnt ? bit : 0u;
+                    if (dir == 0) {
+                        ex |= m;
+                        qx &= ~bit;
+                    } else if (dir == 1) {
+                        ey |= m;
+                        qy &= ~bit;
+                    } else {
+                        ez |= m;
+                        qz &= ~bit;
+                    }
                 }
             }
         }
@@ -194,7 +303,7 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
     auto flush = [&](bool faces) {
         int &cnt = faces ? fcnt : ccnt;
         if (cnt == 0) return;
-        __builtin_amdgcn_wave_barrier();
+        wait_lds();
         unsigned long long base = 0;
         if (lane == 0)
             base = atomicAdd(reinterpret_cast<unsigned long long *>(&A.counts[faces ? 0 : 1]), (unsigned long long)cnt);
@@ -215,7 +324,7 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wait_lds();
         cnt = 0;
     };
     auto append = [&](bool pred, uint64_t entry, bool faces) {
@@ -230,112 +339,130 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
     };
 
     // ---- prologue: plane z0 ----------------------------------------------------------------------
-    uint32_t pi0, nr0;
+    uint32_t pi0, nr0, pih0, nrh0;
+    WT cx0, cy0, cy0h, wz0;
     issue(z0);
-    sign_words(pi0, nr0);
-    issue(z0 + 1);
-    WT cx0, cy0, wz0;
+    wait_vm();
+    sign_words(pi0, nr0, pih0, nrh0);
     {
-        const uint32_t pin = next_lane(pi0), nrn = next_lane(nr0);
-        const uint32_t piy = pi0 >> 1, nry = nr0 >> 1;
-        uint32_t ex, ey, ez;
-        resolve(lane < 63 ? needs_exact(pi0, pin, nr0, nrn) : 0u, needs_exact(pi0, piy, nr0, nry) & 0x7fffffffu, 0u, z0,
-                ex, ey, ez);
-        cx0 = edges(pi0, pin, nr0, nrn, ex);
+        const uint32_t pix = colnext(pi0, pih0, m4), nrx = colnext(nr0, nrh0, m4);
+        const uint32_t piy = next_lane(pi0), nry = next_lane(nr0);
+        const uint32_t pihy = next_lane(pih0), nrhy = next_lane(nrh0);
+        uint32_t ex, ey, ez, ehy, ehz;
+        resolve(needs_exact(pi0, pix, nr0, nrx), needs_exact(pi0, piy, nr0, nry) & minner, 0u,
+                needs_exact(pih0, pihy, nrh0, nrhy) & minner & m4 & 1u, 0u, z0, ex, ey, ez, ehy, ehz);
+        cx0 = edges(pi0, pix, nr0, nrx, ex);
         cy0 = edges(pi0, piy, nr0, nry, ey);
-        wz0 = mask(sum4(cx0, lane_next(cy0), shr1(cx0), cy0), xstep ? ystep : 0u);
+        cy0h = mask(edges(pih0, pihy, nrh0, nrhy, ehy), 1u);
+        wz0 = mask(sum4(cx0, colnext(cy0, cy0h, m4), lane_next(cx0), cy0), ystep ? xstep : 0u);
     }
+    wait_lds();
+    issue(z0 + 1);
 
-    const uint64_t plane_nodes = (uint64_t)nx * (uint64_t)ny;
     for (int k = z0; k < z1; ++k) {
-        uint32_t pi1, nr1;
-        sign_words(pi1, nr1);
-        if (k + 1 < z1) issue(k + 2);
         const bool zstep = A.pz || (k + 1 < nz);
+        wait_vm();
+        uint32_t pi1, nr1, pih1, nrh1;
+        sign_words(pi1, nr1, pih1, nrh1);
 
-        const uint32_t pin = next_lane(pi1), nrn = next_lane(nr1);
-        const uint32_t piy = pi1 >> 1, nry = nr1 >> 1;
-        uint32_t ex, ey, ez;
-        resolve(lane < 63 ? needs_exact(pi1, pin, nr1, nrn) : 0u, needs_exact(pi1, piy, nr1, nry) & 0x7fffffffu,
-                needs_exact(pi0, pi1, nr0, nr1), k + 1, ex, ey, ez);
-        const WT cx1 = edges(pi1, pin, nr1, nrn, ex);
+        const uint32_t pix = colnext(pi1, pih1, m4), nrx = colnext(nr1, nrh1, m4);
+        const uint32_t piy = next_lane(pi1), nry = next_lane(nr1);
+        const uint32_t pihy = next_lane(pih1), nrhy = next_lane(nrh1);
+        uint32_t ex, ey, ez, ehy, ehz;
+        resolve(needs_exact(pi1, pix, nr1, nrx), needs_exact(pi1, piy, nr1, nry) & minner,
+                needs_exact(pi0, pi1, nr0, nr1), needs_exact(pih1, pihy, nrh1, nrhy) & minner & m4 & 1u,
+                needs_exact(pih0, pih1, nrh0, nrh1) & m4 & 1u, k, ex, ey, ez, ehy, ehz);
+        // every LDS read of plane k+1 is done: request plane k+2 into the same buffer
+        wait_lds();
+        if (k + 1 < z1) issue(k + 2);
+
+        const WT cx1 = edges(pi1, pix, nr1, nrx, ex);
         const WT cy1 = edges(pi1, piy, nr1, nry, ey);
         const WT cz = edges(pi0, pi1, nr0, nr1, ez);
+        const WT cy1h = mask(edges(pih1, pihy, nrh1, nrhy, ehy), 1u);
+        const WT czh = mask(edges(pih0, pih1, nrh0, nrh1, ehz), 1u);
 
-        // faces of plane k+1 (w_z) and plane k (w_x, w_y)
-        const WT wz1 = mask(sum4(cx1, lane_next(cy1), shr1(cx1), cy1), xstep ? ystep : 0u);
-        const WT wx = mask(sum4(cy0, shr1(cz), cy1, cz), zstep ? ystep : 0u);
-        const WT wy = mask(sum4(cz, cx1, lane_next(cz), cx0), (zstep && xstep) ? 0xffffffffu : 0u);
+        // faces of plane k+1 (w_z) and plane k (w_x, w_y); halo column's w_x for the last cell
+        const WT wz1 = mask(sum4(cx1, colnext(cy1, cy1h, m4), lane_next(cx1), cy1), ystep ? xstep : 0u);
+        const uint32_t yzm = (ystep && zstep) ? 0xffffffffu : 0u;
+        const WT wx = mask(sum4(cy0, lane_next(cz), cy1, cz), yzm);
+        const WT wxh = mask(sum4(cy0h, lane_next(czh), cy1h, czh), yzm & 1u);
+        const WT wy = mask(sum4(cz, cx1, colnext(cz, czh, m4), cx0), zstep ? xstep : 0u);
 
-        const WT wxn = lane_next(wx);
+        const WT wxr = colnext(wx, wxh, m4);  // w_x at x+1
+        const WT wyu = lane_next(wy);     // w_y at y+1
         const uint32_t nzx = wx.p | wx.n, nzy = wy.p | wy.n, nz0 = wz0.p | wz0.n, nz1 = wz1.p | wz1.n;
-        const uint32_t outm = lane_out ? rvalid : 0u;
-        const uint32_t cellm = (xstep && zstep) ? (ystep & outm) : 0u;
-        const uint32_t pc = (nzx | wxn.p | wxn.n | nzy | (nzy >> 1) | nz0 | nz1) & cellm;
+        const uint32_t outm = row_out ? cvalid : 0u;
+        const uint32_t cellm = (ystep && zstep) ? (xstep & outm) : 0u;
+        const uint32_t pc = (nzx | wxr.p | wxr.n | nzy | wyu.p | wyu.n | nz0 | nz1) & cellm;
 
-        // packed bytes: bit0 w_x != 0, bit1 w_x < 0, bit2/3 w_y, bit4/5 w_z, bit6 pierced cell
-        if (A.wind && lane_out) {
+        // packed bytes of this row: bit0 w_x != 0, bit1 w_x < 0, bit2/3 w_y, bit4/5 w_z, bit6 cell
+        if (A.wind && row_out && ncol > 0) {
             const uint32_t wrd[7] = {nzx, wx.n, nzy, wy.n, nz0, wz0.n, pc};
-            uint8_t *wbase = A.wind + (uint64_t)k * plane_nodes + (uint64_t)xg;
+            uint32_t d[8];
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
-                uint32_t d = 0;
+                uint32_t v = 0;
 #pragma unroll
                 for (int b = 0; b < 7; ++b) {
                     const uint32_t nib = (wrd[b] >> (4 * g)) & 0xfu;
-                    d |= (__umul24(nib, 0x204081u) & 0x01010101u) << b;
+                    v |= (__umul24(nib, 0x204081u) & 0x01010101u) << b;
                 }
+                d[g] = v;
+            }
+            uint8_t *dst = A.wind + (uint64_t)k * plane_nodes + (uint64_t)yg * nx + xl0;
+            if (ncol == 32 && (nx & 15) == 0 && A.wind_a16) {
+                reinterpret_cast<uint4 *>(dst)[0] = make_uint4(d[0], d[1], d[2], d[3]);
+                reinterpret_cast<uint4 *>(dst)[1] = make_uint4(d[4], d[5], d[6], d[7]);
+            } else if (ncol == 32 && (nx & 3) == 0 && A.wind_a4) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 4 * g + i;
-                    if (r < TYO && ((rvalid >> r) & 1u))
-                        __builtin_nontemporal_store((uint8_t)(d >> (8 * i)), wbase + (uint64_t)row_of(r) * nx);
-                }
+                for (int g = 0; g < 8; ++g) reinterpret_cast<uint32_t *>(dst)[g] = d[g];
+            } else {
+                for (int c = 0; c < ncol; ++c) dst[c] = (uint8_t)(d[c >> 2] >> (8 * (c & 3)));
             }
         }
 
         // pierced faces and cells of plane k
         uint32_t fx = nzx & outm, fy = nzy & outm, fz = nz0 & outm, fc = pc;
         if (__ballot((fx | fy | fz | fc) != 0u) != 0) {
-            const WT wyu = shr1(wy);
+            const uint64_t rowbase = (uint64_t)k * plane_nodes + (uint64_t)yg * nx + (uint64_t)xl0;
             while (__ballot((fx | fy | fz | fc) != 0u) != 0) {
-                bool hf = (fx | fy | fz) != 0u;
+                const bool hf = (fx | fy | fz) != 0u;
                 uint64_t fe = 0;
                 if (hf) {
-                    int a, r;
+                    int a, c;
                     uint32_t neg;
                     if (fx) {
                         a = 0;
-                        r = __builtin_ctz(fx);
+                        c = __builtin_ctz(fx);
                         fx &= fx - 1;
                         neg = wx.n;
                     } else if (fy) {
                         a = 1;
-                        r = __builtin_ctz(fy);
+                        c = __builtin_ctz(fy);
                         fy &= fy - 1;
                         neg = wy.n;
                     } else {
                         a = 2;
-                        r = __builtin_ctz(fz);
+                        c = __builtin_ctz(fz);
                         fz &= fz - 1;
                         neg = wz0.n;
                     }
-                    const uint64_t n = (uint64_t)k * plane_nodes + (uint64_t)(y0 + r) * nx + (uint64_t)xg;
-                    fe = ((3 * n + a) << 1) | ((neg >> r) & 1u);
+                    const uint64_t n = rowbase + (uint64_t)c;
+                    fe = ((3 * n + a) << 1) | ((neg >> c) & 1u);
                 }
                 append(hf, fe, true);
                 const bool hc = fc != 0u;
                 uint64_t ce = 0;
                 if (hc) {
-                    const int r = __builtin_ctz(fc);
+                    const int c = __builtin_ctz(fc);
                     fc &= fc - 1;
                     auto e2 = [&](const WT &w) -> uint32_t {
-                        return ((w.p >> r) & 1u) | (((w.n >> r) & 1u) ? 3u : 0u);
+                        return ((w.p >> c) & 1u) | (((w.n >> c) & 1u) ? 3u : 0u);
                     };
-                    const uint32_t desc = e2(wx) | (e2(wxn) << 2) | (e2(wy) << 4) | (e2(wyu) << 6) | (e2(wz0) << 8) |
+                    const uint32_t desc = e2(wx) | (e2(wxr) << 2) | (e2(wy) << 4) | (e2(wyu) << 6) | (e2(wz0) << 8) |
                                           (e2(wz1) << 10);
-                    const uint64_t n = (uint64_t)k * plane_nodes + (uint64_t)(y0 + r) * nx + (uint64_t)xg;
-                    ce = (n << 12) | desc;
+                    ce = ((rowbase + (uint64_t)c) << 12) | desc;
                 }
                 append(hc, ce, false);
             }
@@ -343,8 +470,11 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
 
         pi0 = pi1;
         nr0 = nr1;
+        pih0 = pih1;
+        nrh0 = nrh1;
         cx0 = cx1;
         cy0 = cy1;
+        cy0h = cy1h;
         wz0 = wz1;
     }
     flush(true);
@@ -377,13 +507,16 @@ vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const 
     A.pz = (int)((d.periodic >> 2) & 1u);
     A.ntx = (d.nx + TXO - 1) / TXO;
     A.nty = (d.ny + TYO - 1) / TYO;
+    A.psi_a16 = ((uintptr_t)psi & 15u) == 0;
+    A.wind_a16 = ((uintptr_t)o.d_wind & 15u) == 0;
+    A.wind_a4 = ((uintptr_t)o.d_wind & 3u) == 0;
     int zc = h->wind_zc;
     if (zc <= 0) {
         // planes per chunk: enough tiles to keep every CU busy several times over
         const int64_t cols = (int64_t)A.ntx * A.nty;
         const int64_t want = 16LL * (h->num_cu > 0 ? h->num_cu : 256);
         zc = d.nz;
-        while (zc > 32 && cols * ((d.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
+        while (zc > 16 && cols * ((d.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
     }
     A.zc = zc;
     A.ntz = (d.nz + zc - 1) / zc;
