@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -144,6 +146,16 @@ def main():
     nf, nc = (int(v) for v in out["counts"].cpu())
     if nf > cap or nc > cap:
         raise RuntimeError(f"list capacity {cap} too small: {nf} faces, {nc} cells")
+
+    if args.calib_copy:
+        # kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
+        # (fill: writes 1 GiB; sum: reads 1 GiB)
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        total = float(src.sum())
+        torch.cuda.synchronize()
+        del src, total
 
     vx_profile_enable(ex.h, True)
     torch.cuda.synchronize()

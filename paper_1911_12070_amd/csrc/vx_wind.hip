@@ -338,6 +338,23 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
         cnt += c;
     };
 
+    // ---- deferred packed-byte stores ----------------------------------------------------------------
+    uint32_t pend[8];
+    int pend_k = -1;
+    auto store_pending = [&]() {
+        if (pend_k < 0 || !row_out || ncol == 0) return;
+        uint8_t *dst = A.wind + (uint64_t)pend_k * plane_nodes + (uint64_t)yg * nx + xl0;
+        if (ncol == 32 && (nx & 15) == 0 && A.wind_a16) {
+            reinterpret_cast<uint4 *>(dst)[0] = make_uint4(pend[0], pend[1], pend[2], pend[3]);
+            reinterpret_cast<uint4 *>(dst)[1] = make_uint4(pend[4], pend[5], pend[6], pend[7]);
+        } else if (ncol == 32 && (nx & 3) == 0 && A.wind_a4) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) reinterpret_cast<uint32_t *>(dst)[g] = pend[g];
+        } else {
+            for (int cc = 0; cc < ncol; ++cc) dst[cc] = (uint8_t)(pend[cc >> 2] >> (8 * (cc & 3)));
+        }
+    };
+
     // ---- prologue: plane z0 ----------------------------------------------------------------------
     uint32_t pi0, nr0, pih0, nrh0;
     WT cx0, cy0, cy0h, wz0;
@@ -372,7 +389,9 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
         resolve(needs_exact(pi1, pix, nr1, nrx), needs_exact(pi1, piy, nr1, nry) & minner,
                 needs_exact(pi0, pi1, nr0, nr1), needs_exact(pih1, pihy, nrh1, nrhy) & minner & m4 & 1u,
                 needs_exact(pih0, pih1, nrh0, nrh1) & m4 & 1u, k, ex, ey, ez, ehy, ehz);
-        // every LDS read of plane k+1 is done: request plane k+2 into the same buffer
+        // previous plane's packed bytes, then (every LDS read of plane k+1 being done) request plane
+        // k+2 into the same buffer
+        store_pending();
         wait_lds();
         if (k + 1 < z1) issue(k + 2);
 
@@ -396,10 +415,11 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
         const uint32_t cellm = (ystep && zstep) ? (xstep & outm) : 0u;
         const uint32_t pc = (nzx | wxr.p | wxr.n | nzy | wyu.p | wyu.n | nz0 | nz1) & cellm;
 
-        // packed bytes of this row: bit0 w_x != 0, bit1 w_x < 0, bit2/3 w_y, bit4/5 w_z, bit6 cell
-        if (A.wind && row_out && ncol > 0) {
+        // packed bytes of this row: bit0 w_x != 0, bit1 w_x < 0, bit2/3 w_y, bit4/5 w_z, bit6 cell.
+        // They are written at the start of the next step, before that step's prefetch, so that the
+        // wait for the prefetch never waits on these stores.
+        if (A.wind) {
             const uint32_t wrd[7] = {nzx, wx.n, nzy, wy.n, nz0, wz0.n, pc};
-            uint32_t d[8];
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
                 uint32_t v = 0;
@@ -408,18 +428,9 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
                     const uint32_t nib = (wrd[b] >> (4 * g)) & 0xfu;
                     v |= (__umul24(nib, 0x204081u) & 0x01010101u) << b;
                 }
-                d[g] = v;
+                pend[g] = v;
             }
-            uint8_t *dst = A.wind + (uint64_t)k * plane_nodes + (uint64_t)yg * nx + xl0;
-            if (ncol == 32 && (nx & 15) == 0 && A.wind_a16) {
-                reinterpret_cast<uint4 *>(dst)[0] = make_uint4(d[0], d[1], d[2], d[3]);
-                reinterpret_cast<uint4 *>(dst)[1] = make_uint4(d[4], d[5], d[6], d[7]);
-            } else if (ncol == 32 && (nx & 3) == 0 && A.wind_a4) {
-#pragma unroll
-                for (int g = 0; g < 8; ++g) reinterpret_cast<uint32_t *>(dst)[g] = d[g];
-            } else {
-                for (int c = 0; c < ncol; ++c) dst[c] = (uint8_t)(d[c >> 2] >> (8 * (c & 3)));
-            }
+            pend_k = k;
         }
 
         // pierced faces and cells of plane k
@@ -477,6 +488,7 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
         cy0h = cy1h;
         wz0 = wz1;
     }
+    store_pending();
     flush(true);
     flush(false);
 }
@@ -514,7 +526,7 @@ vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const 
     if (zc <= 0) {
         // planes per chunk: enough tiles to keep every CU busy several times over
         const int64_t cols = (int64_t)A.ntx * A.nty;
-        const int64_t want = 16LL * (h->num_cu > 0 ? h->num_cu : 256);
+        const int64_t want = 128LL * (h->num_cu > 0 ? h->num_cu : 256);
         zc = d.nz;
         while (zc > 16 && cols * ((d.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
     }
