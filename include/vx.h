@@ -170,6 +170,7 @@ typedef struct {
 #define VX_SAMPLE_NONZERO_MIN 8u      /* |psi|^2 > rho_tol at the end */
 #define VX_SAMPLE_NOT_CONVERGED 16u   /* Newton ended without a short step, rho > rho_tol */
 #define VX_SAMPLE_NO_FACES 32u        /* the listed cell has no pierced face */
+#define VX_SAMPLE_BAD_CELL 64u        /* the listed cell id is >= nx*ny*nz: nothing was read */
 
 typedef struct {
     uint64_t cell;    /* cell id */

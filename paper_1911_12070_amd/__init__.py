@@ -23,6 +23,7 @@ SAMPLE_BOUNDARY = 4
 SAMPLE_NONZERO_MIN = 8
 SAMPLE_NOT_CONVERGED = 16
 SAMPLE_NO_FACES = 32
+SAMPLE_BAD_CELL = 64
 
 KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH = 0, 1, 2, 3
 

@@ -26,6 +26,9 @@ struct vx_handle {
     size_t events_used = 0;
     int wind_ty = 0;  // rows per wavefront of the winding kernel (0 = default)
     int wind_zc = 0;  // planes per z-chunk (0 = chosen from the grid)
+    int ref_blocks_per_cu = 0;  // resident refinement workgroups per CU (0 = not yet queried)
+    int ref_refill = 8;         // idle lanes a refinement wavefront waits for before claiming samples
+    unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter
 };
 
 // error helpers -----------------------------------------------------------------------------

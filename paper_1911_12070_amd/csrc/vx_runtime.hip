@@ -62,6 +62,10 @@ extern "C" vx_status vx_create(int device, vx_handle **out) {
         return VX_ERR_DEVICE;
     }
     h->num_cu = prop.multiProcessorCount;
+    if (hipMalloc((void **)&h->d_work, 256) != hipSuccess) {
+        delete h;
+        return VX_ERR_NOMEM;
+    }
     *out = h;
     return VX_OK;
 }
@@ -73,6 +77,7 @@ extern "C" vx_status vx_destroy(vx_handle *h) {
         (void)hipEventDestroy(p.start);
         (void)hipEventDestroy(p.stop);
     }
+    if (h->d_work) (void)hipFree(h->d_work);
     delete h;
     return VX_OK;
 }

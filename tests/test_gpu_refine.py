@@ -80,3 +80,61 @@ def test_refine_tangle_256(ex):
     assert np.median(e) < 1e-5
     # the refined density is near zero where the oracle converged (Sec. 3.3.3: rho = 0 on the core)
     assert np.percentile(s["rho"][ok], 99) < 1e-9
+
+
+def _face_centre_seeds(cdesc):
+    """Mean of the centres of the pierced faces in cell-local coordinates, FP32, faces in the order
+    -x, +x, -y, +y, -z, +z (Sec. 3.3.1 first estimate)."""
+    seeds = np.zeros((len(cdesc), 3), np.float32)
+    for i, d in enumerate(cdesc):
+        acc = np.zeros(3, np.float32)
+        n = 0
+        for f in range(6):
+            if (int(d) >> (2 * f)) & 3:
+                c = np.full(3, 0.5, np.float32)
+                c[f >> 1] = f & 1
+                acc += c
+                n += 1
+        seeds[i] = acc * np.float32(1.0 / n) if n else 0.5
+    return seeds
+
+
+def test_refine_seeds_and_bad_cells(ex):
+    """Caller seeds equal to the face-centre estimate reproduce the unseeded run bit for bit; a seed at
+    the refined position stays there; out-of-range cell ids are flagged and leave the others intact."""
+    import torch
+    from paper_1911_12070_amd import SAMPLE_BAD_CELL, samples_to_numpy
+    t = vxinputs.make_tangle((64, 64, 48), 128, (2, 5), 43)
+    psi = vxinputs.eval_tangle(t)
+    psi_dev = to_dev(psi)
+    out = run_winding(ex, psi_dev, 7)
+    torch.cuda.synchronize()
+    nc = int(out["counts"][1].cpu())
+    assert nc > 100
+    base = samples_to_numpy(ex.refine(psi_dev, out, 7), nc)
+    cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    seeds = torch.from_numpy(_face_centre_seeds(cdesc).reshape(-1)).cuda()
+    seeded = samples_to_numpy(ex.refine(psi_dev, out, 7, seed=seeds), nc)
+    for k in ("cell", "off", "rho", "iters", "status"):
+        assert np.array_equal(seeded[k], base[k]), k
+    seeds2 = torch.from_numpy(np.ascontiguousarray(base["off"], np.float32).reshape(-1)).cuda()
+    again = samples_to_numpy(ex.refine(psi_dev, out, 7, seed=seeds2), nc)
+    good = (base["status"] & BAD) == 0
+    assert np.abs(again["off"] - base["off"]).max(axis=1)[good].max() < 1e-5
+
+    n_nodes = psi.size
+    cells = out["cells"].clone()
+    bad_ids = [n_nodes, n_nodes + 12345, -1]  # -1 reads as 2^64 - 1
+    pos = [0, nc // 2, nc - 1]
+    for p, b in zip(pos, bad_ids):
+        cells[p] = b
+    out2 = dict(out)
+    out2["cells"] = cells
+    mixed = samples_to_numpy(ex.refine(psi_dev, out2, 7), nc)
+    torch.cuda.synchronize()
+    for p in pos:
+        assert mixed["status"][p] == SAMPLE_BAD_CELL
+        assert mixed["rho"][p] == -1.0
+    keep = np.setdiff1d(np.arange(nc), pos)
+    for k in ("off", "rho", "iters", "status"):
+        assert np.array_equal(mixed[k][keep], base[k][keep]), k
