@@ -34,20 +34,27 @@ def kernel_hash() -> str:
 
 
 def traffic_record(grid: int):
-    """HBM bytes per launch of the winding kernel from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "wind_compact_tangle_1024_traffic.json")
+    """HBM bytes per launch of the winding kernel from the committed rocprofv3 counter runs
+    (`key = value` lines), if they were taken on the current kernel source and grid."""
+    path = os.path.join(ROOT, "profiles", "wind_bits_k_tangle_1024_traffic.txt")
+    rec = {}
     try:
         with open(path) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
+            for line in fh:
+                if "=" in line and not line.lstrip().startswith("#"):
+                    k, v = line.split("=", 1)
+                    rec[k.strip()] = v.strip()
+    except OSError:
         return None
-    if rec.get("kernel_sha") != kernel_hash() or rec.get("grid") != grid:
+    if rec.get("kernel_sha") != kernel_hash() or rec.get("grid") != str(grid):
         return None
-    return rec.get("bytes_per_launch")
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
-def cpu_baseline(tangle, block: int = 64, budget_s: float = 10.0):
+def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0):
     """Oracle (plain C, one thread) on a block^3 sub-block of the benchmark field: winding + pierced
     lists of the block (taken as a periodic grid: the per-node work is the same) and refinement of
     every pierced cell. Repeated until `budget_s` of CPU time is spent."""
@@ -70,7 +77,7 @@ def cpu_baseline(tangle, block: int = 64, budget_s: float = 10.0):
         t_r += c - b
         ncell = len(W.cells)
         reps += 1
-        if c - t0 > budget_s or reps >= 50:
+        if c - t0 > budget_s or reps >= 200:
             break
     nodes = block ** 3
     step_s = (t_w + t_r) / reps
@@ -206,7 +213,7 @@ def main():
         "refine_converged_fraction": float(ok.mean()) if len(ok) else None,
         "roofline": {
             "bound": "hbm",
-            "kernel": "wind_compact_k",
+            "kernel": "wind_bits_k",
             "achieved": achieved,
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
