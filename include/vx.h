@@ -189,6 +189,59 @@ vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_
                     int64_t cap, const vx_refine_params *p, vx_sample *d_out, vx_stream s);
 
 /* ------------------------------------------------------------------------------------------
+ * Batching: winding + compaction and refinement of many grids of uneven size (a time series of
+ * frames, Sec. 5 timing over time steps) in one captured HIP graph.
+ *
+ * vx_batch_create validates the frames, builds the per-frame argument tables in device memory
+ * (copied synchronously, once) and captures the work into a graph: the winding of every tile of
+ * every frame is ONE kernel launch over the combined tile range, the refinement of every listed
+ * cell of every frame is ONE launch whose work chunks never straddle frames. Each frame's results
+ * are exactly those of vx_winding + vx_refine on that frame alone (same kernels, same arithmetic).
+ *
+ *   frames[f].d_psi, .dims, .out   as for vx_winding (out.d_counts receives the frame's counts)
+ *   frames[f].d_samples            nullable; vx_sample[sample_cap]: refine the frame's listed cells
+ *                                  (the first min(count, cell_cap, sample_cap) of them)
+ * The buffers named in `frames` must stay allocated while the batch exists; their contents may
+ * change between launches (new psi values, same shapes): that is the point of the replay.
+ * nframes <= VX_BATCH_MAX_FRAMES. Launches of one batch must not overlap in time (they share the
+ * batch's work counter); different batches are independent.
+ * ---------------------------------------------------------------------------------------- */
+#define VX_BATCH_MAX_FRAMES 128
+typedef struct {
+    vx_dims dims;
+    const void *d_psi;
+    vx_winding_out out;
+    vx_sample *d_samples;
+    int64_t sample_cap;
+} vx_frame;
+typedef struct vx_batch vx_batch;
+
+/* p: refinement parameters (NULL = vx_refine_defaults()). The frame table is copied. */
+vx_status vx_batch_create(vx_handle *h, const vx_frame *frames, int nframes, const vx_refine_params *p,
+                          vx_batch **out);
+/* Replay the captured graph on stream s. */
+vx_status vx_batch_launch(vx_batch *b, vx_stream s);
+/* The same kernels launched directly on s, without the graph (for checking the replay). */
+vx_status vx_batch_launch_eager(vx_batch *b, vx_stream s);
+/* Planes per z-chunk used for frame f (after autotuning, the tuned value). */
+vx_status vx_batch_zchunk(const vx_batch *b, int frame, int *zchunk);
+/* Autotune the z-chunk depth of every distinct frame shape for this batch, by coordinate descent
+ * over {8, 16, 32, 64, 128} (values above nz dropped), timing the batched winding launch with HIP
+ * events on s (median of 3 after one warm-up); synchronises s. cache_path (nullable) is a JSON
+ * file of earlier results, one object per line: {"kind": "batch", "dims": [nx, ny, nz],
+ * "periodic": p, "zchunk": z}; entries found there are used without timing, new results are
+ * appended. The graph is captured again with the chosen depths. */
+vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_stream s);
+vx_status vx_batch_destroy(vx_batch *b);
+
+/* Autotune the z-chunk depth of vx_winding for one grid shape on the caller's field d_psi
+ * (same candidates and timing as above, with internal scratch outputs allocated for the
+ * duration of the call; synchronises s); the handle then uses it for that shape.
+ * cache_path as above with "kind": "grid". *zchunk (nullable) receives the choice. */
+vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char *cache_path, int *zchunk,
+                      vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).
  * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate inference, 3 = batch.
  * ---------------------------------------------------------------------------------------- */

@@ -30,7 +30,10 @@ KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH = 0, 1, 2, 3
 # every symbol include/vx.h declares
 EXPORTS = ["vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
-           "vx_profile_enable", "vx_profile_read"]
+           "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
+           "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_profile_enable", "vx_profile_read"]
+
+BATCH_MAX_FRAMES = 128
 
 
 class VxError(RuntimeError):
@@ -75,6 +78,11 @@ class Sample(ctypes.Structure):
 assert ctypes.sizeof(Sample) == 32
 
 
+class Frame(ctypes.Structure):
+    _fields_ = [("dims", Dims), ("d_psi", ctypes.c_void_p), ("out", WindingOut), ("d_samples", ctypes.c_void_p),
+                ("sample_cap", ctypes.c_int64)]
+
+
 def build():
     from . import _build
     return _build.build()
@@ -109,6 +117,20 @@ def lib() -> ctypes.CDLL:
         L.vx_refine_defaults.restype = RefineParams
         L.vx_refine.argtypes = [P, Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
         L.vx_refine.restype = st
+        L.vx_batch_create.argtypes = [P, ctypes.POINTER(Frame), i, ctypes.POINTER(RefineParams), ctypes.POINTER(P)]
+        L.vx_batch_create.restype = st
+        L.vx_batch_launch.argtypes = [P, P]
+        L.vx_batch_launch.restype = st
+        L.vx_batch_launch_eager.argtypes = [P, P]
+        L.vx_batch_launch_eager.restype = st
+        L.vx_batch_zchunk.argtypes = [P, i, ctypes.POINTER(i)]
+        L.vx_batch_zchunk.restype = st
+        L.vx_batch_autotune.argtypes = [P, ctypes.c_char_p, P]
+        L.vx_batch_autotune.restype = st
+        L.vx_batch_destroy.argtypes = [P]
+        L.vx_batch_destroy.restype = st
+        L.vx_autotune.argtypes = [P, Dims, P, ctypes.c_char_p, ctypes.POINTER(i), P]
+        L.vx_autotune.restype = st
         L.vx_profile_enable.argtypes = [P, i]
         L.vx_profile_enable.restype = st
         L.vx_profile_read.argtypes = [P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -199,6 +221,50 @@ def vx_refine(h, d: Dims, psi, cells, cdesc, count, out, params: RefineParams | 
                               ctypes.byref(prm), _ptr(out), _stream(stream)), "vx_refine")
 
 
+def winding_out(counts, wind=None, faces=None, fsign=None, cells=None, cdesc=None) -> WindingOut:
+    return WindingOut(_ptr(wind), _ptr(faces), _ptr(fsign), int(faces.numel()) if faces is not None else 0,
+                      _ptr(cells), _ptr(cdesc), int(cells.numel()) if cells is not None else 0, _ptr(counts))
+
+
+def vx_batch_create(h, frames, params: RefineParams | None = None):
+    """frames: sequence of Frame structures. Returns the batch handle."""
+    arr = (Frame * len(frames))(*frames)
+    b = ctypes.c_void_p()
+    prm = ctypes.byref(params) if params is not None else None
+    _check(h, lib().vx_batch_create(h, arr, len(frames), prm, ctypes.byref(b)), "vx_batch_create")
+    return b
+
+
+def vx_batch_launch(h, b, stream=None):
+    _check(h, lib().vx_batch_launch(b, _stream(stream)), "vx_batch_launch")
+
+
+def vx_batch_launch_eager(h, b, stream=None):
+    _check(h, lib().vx_batch_launch_eager(b, _stream(stream)), "vx_batch_launch_eager")
+
+
+def vx_batch_zchunk(h, b, frame: int) -> int:
+    z = ctypes.c_int()
+    _check(h, lib().vx_batch_zchunk(b, int(frame), ctypes.byref(z)), "vx_batch_zchunk")
+    return z.value
+
+
+def vx_batch_autotune(h, b, cache_path: str | None = None, stream=None):
+    path = cache_path.encode() if cache_path else None
+    _check(h, lib().vx_batch_autotune(b, path, _stream(stream)), "vx_batch_autotune")
+
+
+def vx_batch_destroy(h, b):
+    _check(h, lib().vx_batch_destroy(b), "vx_batch_destroy")
+
+
+def vx_autotune(h, d: Dims, psi, cache_path: str | None = None, stream=None) -> int:
+    z = ctypes.c_int()
+    path = cache_path.encode() if cache_path else None
+    _check(h, lib().vx_autotune(h, d, _ptr(psi), path, ctypes.byref(z), _stream(stream)), "vx_autotune")
+    return z.value
+
+
 def vx_profile_enable(h, enable: bool = True):
     _check(h, lib().vx_profile_enable(h, int(bool(enable))), "vx_profile_enable")
 
@@ -210,4 +276,4 @@ def vx_profile_read(h, kind: int):
     return ms.value, n.value
 
 
-from .pipeline import Extractor, upload_tangle, samples_to_numpy  # noqa: E402,F401
+from .pipeline import Batch, Extractor, upload_tangle, samples_to_numpy  # noqa: E402,F401

@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -26,9 +28,42 @@ struct vx_handle {
     size_t events_used = 0;
     int wind_ty = 0;  // rows per wavefront of the winding kernel (0 = default)
     int wind_zc = 0;  // planes per z-chunk (0 = chosen from the grid)
-    int ref_blocks_per_cu = 0;  // resident refinement workgroups per CU (0 = not yet queried)
-    int ref_refill = 8;         // idle lanes a refinement wavefront waits for before claiming samples
+    int ref_blocks_per_cu = 0;   // resident refinement workgroups per CU (0 = not yet queried)
+    int refb_blocks_per_cu = 0;  // the same for the batched refinement kernel
+    int ref_refill = 8;          // idle lanes a refinement wavefront waits for before claiming samples
     unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter
+    std::map<std::array<int, 4>, int> tuned_zc;  // (nx, ny, nz, periodic) -> planes per z-chunk
+};
+
+// Arguments of the winding kernel for one grid (one frame of a batch).
+struct vx_wind_args {
+    const float2 *psi;
+    uint8_t *wind;
+    uint64_t *faces;
+    int8_t *fsign;
+    int64_t fcap;
+    uint64_t *cells;
+    uint16_t *cdesc;
+    int64_t ccap;
+    int64_t *counts;
+    int nx, ny, nz;
+    int px, py, pz;
+    int ntx, nty, ntz, zc;
+    int psi_a16;   // psi is 16-byte aligned (16-byte loads allowed)
+    int wind_a16;  // packed field 16-byte aligned
+    int wind_a4;   // packed field 4-byte aligned
+};
+
+// One frame of a batched refinement (64 bytes; the kernel keeps the table in LDS).
+struct vx_ref_frame {
+    const float2 *psi;
+    const uint64_t *cells;
+    const uint16_t *desc;
+    const int64_t *count;  // number of listed cells (device)
+    int64_t cap;           // at most this many are refined
+    vx_sample *out;
+    int nx, ny, nz;
+    uint32_t periodic;
 };
 
 // error helpers -----------------------------------------------------------------------------
@@ -48,6 +83,9 @@ struct vx_timer {
 
 // validation
 vx_status vx_check_dims(vx_handle *h, const vx_dims &d);
+vx_status vx_check_winding(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out *out,
+                           const char *who);
+vx_status vx_check_refine_params(vx_handle *h, const vx_refine_params &p);
 
 // kernels (one translation unit each)
 vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o,
@@ -55,3 +93,18 @@ vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const 
 vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
                            const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
                            const vx_refine_params &p, vx_sample *out, hipStream_t s);
+
+// winding arguments of one grid with a given z-chunk depth (0 = the handle's choice); *ntiles
+// receives the number of tiles (workgroups)
+vx_status vx_wind_make_args(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o, int zc,
+                            vx_wind_args *A, int64_t *ntiles);
+// zero the grid's counts and launch its winding kernel
+vx_status vx_wind_enqueue(vx_handle *h, const vx_wind_args &A, int64_t ntiles, hipStream_t s);
+// planes per z-chunk the handle uses for a single grid of these dims
+int vx_wind_zc_for(vx_handle *h, const vx_dims &d);
+// one launch over the tiles of several grids (tables in device memory; tile_start[nframes] = total)
+vx_status vx_wind_batch_enqueue(vx_handle *h, const vx_wind_args *d_frames, const int *d_tile_start, int nframes,
+                                int64_t total_tiles, hipStream_t s);
+// one launch refining the listed cells of several grids (table in device memory)
+vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
+                                  const vx_refine_params &p, unsigned long long *d_counter, hipStream_t s);

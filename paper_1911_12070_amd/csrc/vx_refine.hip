@@ -87,25 +87,76 @@ constexpr int PH_BEGIN = 3;    // a step of the current kind starts at the next 
 constexpr int MODE_DESCENT = 0;  // gradient descent of |psi|^2, halving step rule
 constexpr int MODE_NEWTON = 1;   // Newton on (Re psi, Im psi), halving until |psi|^2 decreases
 
-__global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, int refill_min) {
+// BATCH = false: one grid, described by the kernel arguments. BATCH = true: the frames of a batch,
+// described by a device table copied to LDS; work chunks never straddle frames, and each lane
+// looks up its own sample's frame where the frame matters (corner fetch, output).
+template <bool BATCH>
+__global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_frame *frames, int nframes,
+                                                        int refill_min) {
     // corner cache: corner d (index dx + 2 dy + 4 dz) of the cell cached by thread t at [d][t]
     __shared__ float2 s_corner[8][REF_THREADS];
+    constexpr int NF = BATCH ? VX_BATCH_MAX_FRAMES : 1;
+    __shared__ vx_ref_frame s_fr[NF];
+    __shared__ double s_rnx[NF], s_rnxy[NF];
+    __shared__ int64_t s_items[NF], s_cstart[NF + 1];
     const vx_refine_params &P = A.p;
     const int tid = threadIdx.x;
-    const int64_t n_items = min(*A.count, A.cap);
     const int64_t nwaves = (int64_t)gridDim.x * (REF_THREADS / 64);
     const int64_t wave = (int64_t)blockIdx.x * (REF_THREADS / 64) + (tid >> 6);
-    // samples [next, end) are this wave's unclaimed ones (uniform); chunk w of the list is wave w's
+    int64_t n_items = 0;  // single grid: number of samples
+    if constexpr (BATCH) {
+        // frame table, samples per frame and the prefix of chunks per frame
+        if (tid < nframes) {
+            const vx_ref_frame F = frames[tid];
+            s_fr[tid] = F;
+            const int64_t n = min(*F.count, F.cap);
+            s_items[tid] = n;
+            s_cstart[tid + 1] = (n + REF_CHUNK - 1) / REF_CHUNK;
+            s_rnx[tid] = 1.0 / (double)F.nx;
+            s_rnxy[tid] = 1.0 / ((double)F.nx * (double)F.ny);
+        }
+        if (tid == 0) s_cstart[0] = 0;
+        __syncthreads();
+        for (int off = 1; off < nframes; off <<= 1) {  // inclusive scan of s_cstart[1..nframes]
+            const int64_t add = (tid < nframes && tid >= off) ? s_cstart[tid + 1 - off] : 0;
+            __syncthreads();
+            if (tid < nframes) s_cstart[tid + 1] += add;
+            __syncthreads();
+        }
+    } else {
+        n_items = min(*A.count, A.cap);
+    }
+    // samples [next, end) of frame cf are this wave's unclaimed ones (uniform); chunk w is wave w's
     // first, the rest are handed out in order by the chunk counter
-    int64_t next = min(n_items, wave * REF_CHUNK);
-    int64_t end = min(n_items, next + REF_CHUNK);
-    bool more = true;  // the list may still hold unclaimed chunks
-
-    const uint64_t nx64 = (uint64_t)A.nx, nxy = (uint64_t)A.nx * (uint64_t)A.ny;
-    const uint64_t ncell = nxy * (uint64_t)A.nz;
-    const double rnx = 1.0 / (double)A.nx, rnxy = 1.0 / (double)nxy;
+    int cf = 0;
+    int64_t next = 0, end = 0;
+    bool more = true;  // unclaimed chunks may remain
+    auto claim = [&](int64_t ci) {
+        if constexpr (BATCH) {
+            if (ci >= s_cstart[nframes]) {
+                more = false;
+                next = end = 0;
+                return;
+            }
+            int lo = 0, hi = nframes;  // last frame whose first chunk is <= ci
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_cstart[mid] <= ci) lo = mid;
+                else hi = mid;
+            }
+            cf = lo;
+            next = (ci - s_cstart[lo]) * REF_CHUNK;
+            end = min(s_items[lo], next + REF_CHUNK);
+        } else {
+            next = min(n_items, ci * REF_CHUNK);
+            end = min(n_items, next + REF_CHUNK);
+            more = next < end;
+        }
+    };
+    claim(wave);
 
     int phase = PH_IDLE, mode = MODE_DESCENT;
+    int fr = 0;  // frame of this lane's sample
     int64_t s = 0;
     uint64_t cell = 0;
     uint32_t desc = 0;
@@ -130,11 +181,8 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, int refill_mi
         if (next >= end && more && (n_idle >= refill_min || n_idle == 64)) {
             unsigned long long c = 0;
             if ((tid & 63) == 0) c = atomicAdd(A.chunks, 1ull);
-            const int64_t ci = (int64_t)nwaves + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane(
-                                   (uint32_t)(c >> 32)) << 32) | __builtin_amdgcn_readfirstlane((uint32_t)c));
-            next = min(n_items, ci * REF_CHUNK);
-            end = min(n_items, next + REF_CHUNK);
-            more = next < end;
+            claim((int64_t)nwaves + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c >> 32)) << 32) |
+                                              __builtin_amdgcn_readfirstlane((uint32_t)c)));
         }
         if (next < end && (n_idle >= refill_min || n_idle == 64)) {
             if (phase == PH_IDLE) {
@@ -142,23 +190,48 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, int refill_mi
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
                 const int64_t mine = next + (int64_t)rank;
                 if (mine < end) {
+                    // the claimed chunk's frame (uniform)
+                    const uint64_t *cells_p = A.cells;
+                    const uint16_t *desc_p = A.desc;
+                    vx_sample *out_p = A.out;
+                    int fnx = A.nx, fny = A.ny, fnz = A.nz, fpx = A.px, fpy = A.py, fpz = A.pz;
+                    double rnx, rnxy;
+                    if constexpr (BATCH) {
+                        const vx_ref_frame &F = s_fr[cf];
+                        cells_p = F.cells;
+                        desc_p = F.desc;
+                        out_p = F.out;
+                        fnx = F.nx;
+                        fny = F.ny;
+                        fnz = F.nz;
+                        fpx = (int)(F.periodic & 1u);
+                        fpy = (int)((F.periodic >> 1) & 1u);
+                        fpz = (int)((F.periodic >> 2) & 1u);
+                        rnx = s_rnx[cf];
+                        rnxy = s_rnxy[cf];
+                    } else {
+                        rnx = 1.0 / (double)A.nx;
+                        rnxy = 1.0 / ((double)A.nx * (double)A.ny);
+                    }
+                    const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
                     s = mine;
-                    cell = A.cells[s];
-                    desc = A.desc[s];
-                    if (cell >= ncell) {
+                    fr = cf;
+                    cell = cells_p[s];
+                    desc = desc_p[s];
+                    if (cell >= nxy * (uint64_t)fnz) {
                         vx_sample o{};
                         o.cell = cell;
                         o.rho = -1.f;
                         o.status = (uint16_t)VX_SAMPLE_BAD_CELL;
-                        A.out[s] = o;
+                        out_p[s] = o;
                     } else {
                         uint64_t rxy, ri;
                         gk = (int)divmod53(cell, nxy, rnxy, rxy);
                         gj = (int)divmod53(rxy, nx64, rnx, ri);
                         gi = (int)ri;
                         const int g3[3] = {gi, gj, gk};
-                        const int n3[3] = {A.nx, A.ny, A.nz};
-                        const int p3[3] = {A.px, A.py, A.pz};
+                        const int n3[3] = {fnx, fny, fnz};
+                        const int p3[3] = {fpx, fpy, fpz};
                         ext = 0;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
@@ -224,16 +297,29 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, int refill_mi
             const int code = (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
             if (code != ccode) {
                 ccode = code;
-                const int64_t i0 = wrap((int64_t)gi + c[0], A.nx, A.px);
-                const int64_t i1 = wrap((int64_t)gi + c[0] + 1, A.nx, A.px);
-                const int64_t j0 = wrap((int64_t)gj + c[1], A.ny, A.py);
-                const int64_t j1 = wrap((int64_t)gj + c[1] + 1, A.ny, A.py);
-                const int64_t k0 = wrap((int64_t)gk + c[2], A.nz, A.pz);
-                const int64_t k1 = wrap((int64_t)gk + c[2] + 1, A.nz, A.pz);
-                const float2 *r00 = A.psi + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
-                const float2 *r10 = A.psi + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
-                const float2 *r01 = A.psi + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
-                const float2 *r11 = A.psi + nx64 * (uint64_t)j1 + nxy * (uint64_t)k1;
+                const float2 *psi_p = A.psi;
+                int fnx = A.nx, fny = A.ny, fnz = A.nz, fpx = A.px, fpy = A.py, fpz = A.pz;
+                if constexpr (BATCH) {
+                    const vx_ref_frame &F = s_fr[fr];
+                    psi_p = F.psi;
+                    fnx = F.nx;
+                    fny = F.ny;
+                    fnz = F.nz;
+                    fpx = (int)(F.periodic & 1u);
+                    fpy = (int)((F.periodic >> 1) & 1u);
+                    fpz = (int)((F.periodic >> 2) & 1u);
+                }
+                const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
+                const int64_t i0 = wrap((int64_t)gi + c[0], fnx, fpx);
+                const int64_t i1 = wrap((int64_t)gi + c[0] + 1, fnx, fpx);
+                const int64_t j0 = wrap((int64_t)gj + c[1], fny, fpy);
+                const int64_t j1 = wrap((int64_t)gj + c[1] + 1, fny, fpy);
+                const int64_t k0 = wrap((int64_t)gk + c[2], fnz, fpz);
+                const int64_t k1 = wrap((int64_t)gk + c[2] + 1, fnz, fpz);
+                const float2 *r00 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
+                const float2 *r10 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
+                const float2 *r01 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
+                const float2 *r11 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k1;
                 const float2 c0 = r00[i0], c1 = r00[i1], c2 = r10[i0], c3 = r10[i1];
                 const float2 c4 = r01[i0], c5 = r01[i1], c6 = r11[i0], c7 = r11[i1];
                 s_corner[0][tid] = c0;
@@ -436,13 +522,31 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, int refill_mi
             o.iters = (uint16_t)min(iters, 65535);
             o.status = (uint16_t)status;
             o.reserved = 0;
-            A.out[s] = o;
+            if constexpr (BATCH) s_fr[fr].out[s] = o;
+            else A.out[s] = o;
             phase = PH_IDLE;
         }
     }
 }
 
 __global__ void zero_u64_k(unsigned long long *p) { *p = 0ull; }
+
+// one resident round of wavefronts (they claim chunks dynamically); fewer for short lists; -1 on error
+template <typename K>
+int64_t ref_blocks(vx_handle *h, K kernel, int &per_cu, int64_t cap) {
+    if (per_cu <= 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, REF_THREADS, 0);
+        if (e != hipSuccess) {
+            vx_hip_check(h, e, "refine_k occupancy");
+            return -1;
+        }
+        per_cu = nb > 0 ? nb : 1;
+    }
+    const int64_t resident = (int64_t)per_cu * (h->num_cu > 0 ? h->num_cu : 256);
+    const int64_t need = (cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);  // >= one chunk per wavefront
+    return std::max<int64_t>(1, std::min(need, resident));
+}
 
 }  // namespace
 
@@ -465,19 +569,27 @@ vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, cons
     A.py = (int)((d.periodic >> 1) & 1u);
     A.pz = (int)((d.periodic >> 2) & 1u);
     A.p = p;
-    // one resident round of wavefronts (each walks its own range of the list); fewer for short lists
-    if (h->ref_blocks_per_cu <= 0) {
-        int nb = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, refine_k, REF_THREADS, 0);
-        if (e != hipSuccess) return vx_hip_check(h, e, "refine_k occupancy");
-        h->ref_blocks_per_cu = nb > 0 ? nb : 1;
-    }
-    const int64_t resident = (int64_t)h->ref_blocks_per_cu * (h->num_cu > 0 ? h->num_cu : 256);
-    const int64_t need = (cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);  // >= one chunk per wavefront
-    const int64_t blocks = std::max<int64_t>(1, std::min(need, resident));
+    const int64_t blocks = ref_blocks(h, refine_k<false>, h->ref_blocks_per_cu, cap);
+    if (blocks < 0) return VX_ERR_DEVICE;
     vx_timer tm(h, s, VX_KIND_REFINE);
     hipLaunchKernelGGL(zero_u64_k, dim3(1), dim3(1), 0, s, h->d_work);
-    hipLaunchKernelGGL(refine_k, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A, h->ref_refill);
+    hipLaunchKernelGGL(refine_k<false>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A,
+                       (const vx_ref_frame *)nullptr, 1, h->ref_refill);
     tm.stop();
     return vx_hip_check(h, hipGetLastError(), "refine_k launch");
+}
+
+vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
+                                  const vx_refine_params &p, unsigned long long *d_counter, hipStream_t s) {
+    if (nframes < 1 || nframes > VX_BATCH_MAX_FRAMES)
+        return vx_fail(h, VX_ERR_INVALID, "refine batch: %d frames", nframes);
+    RefArgs A{};
+    A.chunks = d_counter;
+    A.p = p;
+    const int64_t blocks = ref_blocks(h, refine_k<true>, h->refb_blocks_per_cu, total_cap);
+    if (blocks < 0) return VX_ERR_DEVICE;
+    hipLaunchKernelGGL(zero_u64_k, dim3(1), dim3(1), 0, s, d_counter);
+    hipLaunchKernelGGL(refine_k<true>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A, d_frames, nframes,
+                       h->ref_refill);
+    return vx_hip_check(h, hipGetLastError(), "refine_k batch launch");
 }

@@ -161,20 +161,34 @@ vx_status vx_check_dims(vx_handle *h, const vx_dims &d) {
 }
 
 // ------------------------------------------------------------------------------- entry points
+vx_status vx_check_winding(vx_handle *h, const vx_dims &dims, const void *d_psi, const vx_winding_out *out,
+                           const char *who) {
+    if (!d_psi || !out) return vx_fail(h, VX_ERR_INVALID, "%s: null psi or out", who);
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (((uintptr_t)d_psi & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "%s: psi must be 8-byte aligned", who);
+    if (!out->d_counts) return vx_fail(h, VX_ERR_INVALID, "%s: d_counts is required", who);
+    if (((uintptr_t)out->d_counts & 7u) != 0)
+        return vx_fail(h, VX_ERR_INVALID, "%s: d_counts must be 8-byte aligned", who);
+    if (out->face_cap < 0 || out->cell_cap < 0) return vx_fail(h, VX_ERR_INVALID, "%s: negative capacity", who);
+    if (out->face_cap > 0 && (!out->d_faces || !out->d_face_sign))
+        return vx_fail(h, VX_ERR_INVALID, "%s: face_cap > 0 needs d_faces and d_face_sign", who);
+    if (out->cell_cap > 0 && (!out->d_cells || !out->d_cell_desc))
+        return vx_fail(h, VX_ERR_INVALID, "%s: cell_cap > 0 needs d_cells and d_cell_desc", who);
+    return VX_OK;
+}
+
+vx_status vx_check_refine_params(vx_handle *h, const vx_refine_params &prm) {
+    if (prm.max_descent < 0 || prm.max_newton < 0 || prm.max_halvings < 0 || prm.max_descent > 100000 ||
+        prm.max_newton > 100000 || prm.max_halvings > 200 || !(prm.step0 > 0.f) || !(prm.step_max > 0.f))
+        return vx_fail(h, VX_ERR_INVALID, "refine: bad parameters");
+    return VX_OK;
+}
+
 extern "C" vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_winding_out *out,
                                 vx_stream s) {
     if (!h) return VX_ERR_INVALID;
     h->err.clear();
-    if (!d_psi || !out) return vx_fail(h, VX_ERR_INVALID, "vx_winding: null psi or out");
-    if (vx_status st = vx_check_dims(h, dims)) return st;
-    if (((uintptr_t)d_psi & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "psi must be 8-byte aligned");
-    if (!out->d_counts) return vx_fail(h, VX_ERR_INVALID, "vx_winding: d_counts is required");
-    if (((uintptr_t)out->d_counts & 7u) != 0) return vx_fail(h, VX_ERR_INVALID, "d_counts must be 8-byte aligned");
-    if (out->face_cap < 0 || out->cell_cap < 0) return vx_fail(h, VX_ERR_INVALID, "negative capacity");
-    if (out->face_cap > 0 && (!out->d_faces || !out->d_face_sign))
-        return vx_fail(h, VX_ERR_INVALID, "face_cap > 0 needs d_faces and d_face_sign");
-    if (out->cell_cap > 0 && (!out->d_cells || !out->d_cell_desc))
-        return vx_fail(h, VX_ERR_INVALID, "cell_cap > 0 needs d_cells and d_cell_desc");
+    if (vx_status st = vx_check_winding(h, dims, d_psi, out, "vx_winding")) return st;
     if (vx_status st = vx_bind(h)) return st;
     return vx_wind_launch(h, dims, d_psi, *out, (hipStream_t)s);
 }
@@ -205,9 +219,7 @@ extern "C" vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, co
     if (!d_psi || !d_cells || !d_cell_desc || !d_count || !d_out)
         return vx_fail(h, VX_ERR_INVALID, "vx_refine: null pointer argument");
     vx_refine_params prm = p ? *p : vx_refine_defaults();
-    if (prm.max_descent < 0 || prm.max_newton < 0 || prm.max_halvings < 0 || prm.max_descent > 100000 ||
-        prm.max_newton > 100000 || prm.max_halvings > 200 || !(prm.step0 > 0.f) || !(prm.step_max > 0.f))
-        return vx_fail(h, VX_ERR_INVALID, "vx_refine: bad parameters");
+    if (vx_status st = vx_check_refine_params(h, prm)) return st;
     if (vx_status st = vx_bind(h)) return st;
     return vx_refine_launch(h, dims, d_psi, d_cells, d_cell_desc, d_seed_off, d_count, cap, prm, d_out,
                             (hipStream_t)s);

@@ -39,23 +39,7 @@ constexpr int TYO = 15;    // output rows per tile (16 loaded)
 constexpr int LBUF = 256;  // LDS list entries per list
 constexpr int PLANE_LDS = 16 * 1024;  // bytes of one plane tile in LDS (halo column follows)
 
-struct WindArgs {
-    const float2 *psi;
-    uint8_t *wind;
-    uint64_t *faces;
-    int8_t *fsign;
-    int64_t fcap;
-    uint64_t *cells;
-    uint16_t *cdesc;
-    int64_t ccap;
-    int64_t *counts;
-    int nx, ny, nz;
-    int px, py, pz;
-    int ntx, nty, ntz, zc;
-    int psi_a16;   // psi is 16-byte aligned (16-byte loads allowed)
-    int wind_a16;  // packed field 16-byte aligned
-    int wind_a4;   // packed field 4-byte aligned
-};
+using WindArgs = vx_wind_args;
 
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int per = nb / 8, rem = nb % 8;
@@ -133,13 +117,13 @@ __device__ __forceinline__ uint32_t piece_off(int r, int q) {
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
-__global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
+// One tile (16 rows x 128 columns x one z-chunk) of one grid, run by one wavefront.
+__device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
     __shared__ __attribute__((aligned(16))) uint8_t s_plane[PLANE_LDS + 512];
     __shared__ uint64_t s_fbuf[LBUF];
     __shared__ uint64_t s_cbuf[LBUF];
 
     const int lane = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % A.ntx;
     const int t2 = tile / A.ntx;
     const int ty = t2 % A.nty;
@@ -493,14 +477,53 @@ __global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) {
     flush(false);
 }
 
+__global__ __launch_bounds__(64) void wind_bits_k(WindArgs A) { wind_tile(A, xcd_tile(blockIdx.x, gridDim.x)); }
+
+// Several grids in one launch: the tiles of frame f are numbers tile_start[f] .. tile_start[f+1]-1
+// of one combined range (renumbered per XCD as for a single grid); each workgroup finds its frame by
+// binary search and reads that frame's arguments from the device table.
+__global__ __launch_bounds__(64) void wind_batch_k(const WindArgs *__restrict__ frames,
+                                                   const int *__restrict__ tile_start, int nframes) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = nframes;  // invariant: tile_start[lo] <= t < tile_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const WindArgs A = frames[lo];
+    wind_tile(A, t - tile_start[lo]);
+}
+
 __global__ void zero_counts_k(int64_t *c) {
     if (threadIdx.x < 2) c[threadIdx.x] = 0;
 }
 
+// zero the two counts of every frame of a batch
+__global__ void zero_batch_counts_k(const WindArgs *__restrict__ frames, int nframes) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < nframes) {
+        frames[f].counts[0] = 0;
+        frames[f].counts[1] = 0;
+    }
+}
+
 }  // namespace
 
-vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o,
-                         hipStream_t s) {
+int vx_wind_zc_for(vx_handle *h, const vx_dims &d) {
+    if (h->wind_zc > 0) return h->wind_zc;
+    const auto it = h->tuned_zc.find({d.nx, d.ny, d.nz, (int)d.periodic});
+    if (it != h->tuned_zc.end()) return it->second;
+    // planes per chunk: enough tiles to keep every CU busy several times over
+    const int64_t cols = (int64_t)((d.nx + TXO - 1) / TXO) * ((d.ny + TYO - 1) / TYO);
+    const int64_t want = 128LL * (h->num_cu > 0 ? h->num_cu : 256);
+    int zc = d.nz;
+    while (zc > 16 && cols * ((d.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
+    return zc;
+}
+
+vx_status vx_wind_make_args(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o, int zc,
+                            vx_wind_args *out, int64_t *ntiles) {
     WindArgs A;
     A.psi = (const float2 *)psi;
     A.wind = o.d_wind;
@@ -522,21 +545,37 @@ vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const 
     A.psi_a16 = ((uintptr_t)psi & 15u) == 0;
     A.wind_a16 = ((uintptr_t)o.d_wind & 15u) == 0;
     A.wind_a4 = ((uintptr_t)o.d_wind & 3u) == 0;
-    int zc = h->wind_zc;
-    if (zc <= 0) {
-        // planes per chunk: enough tiles to keep every CU busy several times over
-        const int64_t cols = (int64_t)A.ntx * A.nty;
-        const int64_t want = 128LL * (h->num_cu > 0 ? h->num_cu : 256);
-        zc = d.nz;
-        while (zc > 16 && cols * ((d.nz + zc - 1) / zc) < want) zc = (zc + 1) / 2;
-    }
+    if (zc <= 0) zc = vx_wind_zc_for(h, d);
     A.zc = zc;
     A.ntz = (d.nz + zc - 1) / zc;
     const int64_t nblocks = (int64_t)A.ntx * A.nty * A.ntz;
-    if (nblocks > 2147483647LL) return vx_fail(h, VX_ERR_UNSUPPORTED, "vx_winding: too many tiles");
-    hipLaunchKernelGGL(zero_counts_k, dim3(1), dim3(64), 0, s, o.d_counts);
+    if (nblocks > 2147483647LL) return vx_fail(h, VX_ERR_UNSUPPORTED, "winding: too many tiles");
+    *out = A;
+    *ntiles = nblocks;
+    return VX_OK;
+}
+
+vx_status vx_wind_enqueue(vx_handle *h, const vx_wind_args &A, int64_t ntiles, hipStream_t s) {
+    hipLaunchKernelGGL(zero_counts_k, dim3(1), dim3(64), 0, s, A.counts);
     vx_timer tm(h, s, VX_KIND_WIND);
-    hipLaunchKernelGGL(wind_bits_k, dim3((unsigned)nblocks), dim3(64), 0, s, A);
+    if (ntiles > 0) hipLaunchKernelGGL(wind_bits_k, dim3((unsigned)ntiles), dim3(64), 0, s, A);
     tm.stop();
     return vx_hip_check(h, hipGetLastError(), "wind_bits_k launch");
+}
+
+vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o,
+                         hipStream_t s) {
+    WindArgs A;
+    int64_t nblocks = 0;
+    if (vx_status st = vx_wind_make_args(h, d, psi, o, 0, &A, &nblocks)) return st;
+    return vx_wind_enqueue(h, A, nblocks, s);
+}
+
+vx_status vx_wind_batch_enqueue(vx_handle *h, const vx_wind_args *d_frames, const int *d_tile_start, int nframes,
+                                int64_t total_tiles, hipStream_t s) {
+    if (total_tiles > 2147483647LL) return vx_fail(h, VX_ERR_UNSUPPORTED, "winding batch: too many tiles");
+    hipLaunchKernelGGL(zero_batch_counts_k, dim3((nframes + 63) / 64), dim3(64), 0, s, d_frames, nframes);
+    if (total_tiles > 0)
+        hipLaunchKernelGGL(wind_batch_k, dim3((unsigned)total_tiles), dim3(64), 0, s, d_frames, d_tile_start, nframes);
+    return vx_hip_check(h, hipGetLastError(), "wind_batch_k launch");
 }

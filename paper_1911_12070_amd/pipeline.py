@@ -116,3 +116,56 @@ class Extractor:
                   wout["counts"][1:], samples, params or vx_refine_defaults(), seed, stream,
                   cap=min(cap, samples.shape[0]))
         return samples
+
+
+class Batch:
+    """A vx_batch over frames (psi tensors of uneven shapes) with torch-allocated outputs.
+
+    frames: list of (psi, periodic). Outputs per frame: dict as from Extractor.alloc_winding plus
+    "samples" (sample_cap rows) when refine is set.
+    """
+
+    def __init__(self, ex: Extractor, frames, face_cap=None, cell_cap=None, wind: bool = True,
+                 refine: bool = True, params=None):
+        from . import Frame, dims as make_dims_, winding_out, vx_batch_create
+        self.ex = ex
+        self.psi = [p for p, _ in frames]
+        self.outs = []
+        structs = []
+        for psi, periodic in frames:
+            nz, ny, nx = psi.shape
+            n = nx * ny * nz
+            fc = face_cap(n) if callable(face_cap) else (face_cap or max(4096, n // 16))
+            cc = cell_cap(n) if callable(cell_cap) else (cell_cap or max(4096, n // 16))
+            o = ex.alloc_winding(psi.shape, face_cap=fc, cell_cap=cc, wind=wind)
+            if refine:
+                o["samples"] = ex.alloc_samples(cc)
+            self.outs.append(o)
+            wo = winding_out(o["counts"], o["wind"], o["faces"], o["fsign"], o["cells"], o["cdesc"])
+            structs.append(Frame(make_dims_(nx, ny, nz, periodic), psi.data_ptr(), wo,
+                                 o["samples"].data_ptr() if refine else None, cc if refine else 0))
+        self.b = vx_batch_create(ex.h, structs, params)
+
+    def launch(self, stream=None, graph: bool = True):
+        from . import vx_batch_launch, vx_batch_launch_eager
+        (vx_batch_launch if graph else vx_batch_launch_eager)(self.ex.h, self.b, stream)
+
+    def autotune(self, cache_path=None, stream=None):
+        from . import vx_batch_autotune
+        vx_batch_autotune(self.ex.h, self.b, cache_path, stream)
+
+    def zchunk(self, frame: int) -> int:
+        from . import vx_batch_zchunk
+        return vx_batch_zchunk(self.ex.h, self.b, frame)
+
+    def close(self):
+        from . import vx_batch_destroy
+        if self.b is not None:
+            vx_batch_destroy(self.ex.h, self.b)
+            self.b = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
