@@ -11,6 +11,10 @@ duration measured with HIP events on the launch stream inside the timed region. 
 the CPU oracle (single-threaded C) timed on a sub-block of the same field.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+
+With --workload series_64 it measures batching instead: 64 frames of uneven size (128^3 to 384^3,
+one 1024-wave tangle advanced in time, 1.32e9 cells in all), winding + compaction + refinement of
+every frame in one HIP graph launch per step (z-chunk depths autotuned before timing).
 """
 from __future__ import annotations
 
@@ -54,7 +58,7 @@ def traffic_record(grid: int):
         return None
 
 
-def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0):
+def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0, label: str | None = None):
     """Oracle (plain C, one thread) on a block^3 sub-block of the benchmark field: winding + pierced
     lists of the block (taken as a periodic grid: the per-node work is the same) and refinement of
     every pierced cell. Repeated until `budget_s` of CPU time is spent."""
@@ -86,7 +90,7 @@ def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0):
         "unit": "cells/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{block}^3 sub-block of the benchmark field ({nodes} cells, {ncell} pierced); winding + "
+        "sample": f"{label or f'{block}^3 sub-block of the benchmark field'} ({nodes} cells, {ncell} pierced); winding + "
                   f"pierced lists + FP64 refinement of every pierced cell; {reps} repetitions, "
                   f"{t_w + t_r:.1f} s total",
         "winding_cells_per_s": nodes * reps / t_w,
@@ -94,11 +98,118 @@ def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0):
     }
 
 
+def calib_copy():
+    """Kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
+    (fill: writes 1 GiB; sum: reads 1 GiB)."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    total = float(src.sum())
+    torch.cuda.synchronize()
+    del src, total
+
+
+def bench_series(args):
+    import numpy as np
+    import torch
+
+    import vxinputs
+    from paper_1911_12070_amd import (KIND_REFINE, KIND_WIND, Batch, Extractor, samples_to_numpy,
+                                      vx_profile_enable, vx_profile_read)
+
+    series = vxinputs.series_64()
+    ex = Extractor(0)
+    print("[bench] generating 64 frames on the GPU", file=sys.stderr, flush=True)
+    tangles = [series.frame(f) for f in range(64)]
+    psis = [ex.gen_tangle(t) for t in tangles]
+    batch = Batch(ex, [(p, 7) for p in psis])
+    stream = torch.cuda.current_stream()
+    print("[bench] autotuning z-chunk depths", file=sys.stderr, flush=True)
+    batch.autotune(None, stream)
+    tuned = {t.dims[0]: batch.zchunk(f) for f, t in enumerate(tangles)}
+    for _ in range(args.warmup):
+        batch.launch(stream)
+    torch.cuda.synchronize()
+    counts = [tuple(int(v) for v in o["counts"].cpu()) for o in batch.outs]
+    for (nf, nc), o in zip(counts, batch.outs):
+        if nf > o["faces"].numel() or nc > o["cells"].numel():
+            raise RuntimeError("list capacity too small")
+    if args.calib_copy:
+        calib_copy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.launch(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # per-kernel durations from eager launches of the same kernels (HIP events on the stream)
+    vx_profile_enable(ex.h, True)
+    for _ in range(5):
+        batch.launch(stream, graph=False)
+    wind_ms, nw = vx_profile_read(ex.h, KIND_WIND)
+    ref_ms, nr = vx_profile_read(ex.h, KIND_REFINE)
+    vx_profile_enable(ex.h, False)
+    wind_avg, ref_avg = wind_ms / max(nw, 1), ref_ms / max(nr, 1)
+    cells = sum(int(np.prod(t.dims)) for t in tangles)
+    nf_all = sum(c[0] for c in counts)
+    nc_all = sum(c[1] for c in counts)
+    alg_bytes = cells * 9 + nf_all * 9 + nc_all * 10 + 64 * 16
+    achieved = alg_bytes / (wind_avg * 1e-3) / 1e9
+    ok = np.concatenate([(samples_to_numpy(o["samples"], c[1])["status"] & (8 | 16 | 32)) == 0
+                         for o, c in zip(batch.outs, counts)])
+    res = {
+        "metric": METRIC,
+        "value": cells * args.steps / elapsed,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "series_64: 64 frames, sizes drawn from {128,192,256,384}^3 (seed 4), one 1024-wave "
+                        "tangle (|n| in [4,12]) advanced by exp(-i |n|^2 t / 2), t = 0.05 f; winding + compaction "
+                        "+ refinement of every frame in one HIP graph launch",
+            "cells": cells,
+            "frames_per_size": {str(k): series.sizes.count(k) for k in sorted(set(series.sizes))},
+            "zchunk_per_size": {str(k): v for k, v in sorted(tuned.items())},
+            "pierced_faces": nf_all,
+            "pierced_cells": nc_all,
+        },
+        "samples_per_s": nc_all * args.steps / elapsed,
+        "kernel_ms": {"wind_batch": wind_avg, "refine_batch": ref_avg},
+        "refine_converged_fraction": float(ok.mean()) if len(ok) else None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "wind_batch_k",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        f128 = next(t for t in tangles if t.dims[0] == 128)
+        res["cpu_baseline"] = cpu_baseline(f128, block=128, label="one whole 128^3 frame of the series")
+    batch.close()
+    ex.close()
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["tangle_1024", "series_64"], default="tangle_1024")
     ap.add_argument("--grid", type=int, default=1024)
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
@@ -122,6 +233,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "series_64":
+        return bench_series(args)
 
     N = args.grid
     if N == 1024:
@@ -155,14 +268,7 @@ def main():
         raise RuntimeError(f"list capacity {cap} too small: {nf} faces, {nc} cells")
 
     if args.calib_copy:
-        # kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
-        # (fill: writes 1 GiB; sum: reads 1 GiB)
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        total = float(src.sum())
-        torch.cuda.synchronize()
-        del src, total
+        calib_copy()
 
     vx_profile_enable(ex.h, True)
     torch.cuda.synchronize()

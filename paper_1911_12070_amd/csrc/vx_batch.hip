@@ -172,10 +172,20 @@ vx_status enqueue_wind(vx_batch *b, hipStream_t s) {
     return vx_wind_batch_enqueue(b->h, b->d_wargs, b->d_tile_start, (int)b->frames.size(), b->total_tiles, s);
 }
 
-vx_status enqueue(vx_batch *b, hipStream_t s) {
-    if (vx_status st = enqueue_wind(b, s)) return st;
-    if (b->n_ref > 0) return vx_refine_batch_enqueue(b->h, b->d_rframes, b->n_ref, b->total_cap, b->p, b->d_counter, s);
-    return VX_OK;
+// timed: record the winding and refinement launches separately (eager launches only, never inside
+// a capture)
+vx_status enqueue(vx_batch *b, hipStream_t s, bool timed = false) {
+    {
+        vx_timer tm(b->h, s, timed ? VX_KIND_WIND : -1);
+        const vx_status st = enqueue_wind(b, s);
+        tm.stop();
+        if (st) return st;
+    }
+    if (b->n_ref == 0) return VX_OK;
+    vx_timer tm(b->h, s, timed ? VX_KIND_REFINE : -1);
+    const vx_status st = vx_refine_batch_enqueue(b->h, b->d_rframes, b->n_ref, b->total_cap, b->p, b->d_counter, s);
+    tm.stop();
+    return st;
 }
 
 vx_status capture(vx_batch *b) {
@@ -274,7 +284,7 @@ extern "C" vx_status vx_batch_launch_eager(vx_batch *b, vx_stream s) {
     h->err.clear();
     if (vx_status st = vx_bind(h)) return st;
     vx_timer tm(h, (hipStream_t)s, VX_KIND_BATCH);
-    const vx_status st = enqueue(b, (hipStream_t)s);
+    const vx_status st = enqueue(b, (hipStream_t)s, true);
     tm.stop();
     return st;
 }

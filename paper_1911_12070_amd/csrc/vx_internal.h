@@ -71,12 +71,13 @@ vx_status vx_fail(vx_handle *h, vx_status st, const char *fmt, ...);
 vx_status vx_hip_check(vx_handle *h, hipError_t e, const char *what);
 vx_status vx_bind(vx_handle *h);  // make the handle's device current
 
-// timing helpers: record a start/stop pair around a launch when profiling is on
+// timing helpers: record a start/stop pair around a launch when profiling is on (kind < 0: off).
+// Timers may nest; each keeps the index of its pair (the pool may grow meanwhile).
 struct vx_timer {
     vx_handle *h;
     hipStream_t s;
     int kind;
-    vx_event_pair *pair = nullptr;
+    int64_t slot = -1;
     vx_timer(vx_handle *h_, hipStream_t s_, int kind_);
     void stop();
 };

@@ -86,7 +86,7 @@ extern "C" const char *vx_last_error(const vx_handle *h) { return h ? h->err.c_s
 
 // ------------------------------------------------------------------------------- timing
 vx_timer::vx_timer(vx_handle *h_, hipStream_t s_, int kind_) : h(h_), s(s_), kind(kind_) {
-    if (!h->profile) return;
+    if (!h->profile || kind < 0) return;
     if (h->events_used == h->events.size()) {
         vx_event_pair p{};
         if (hipEventCreate(&p.start) != hipSuccess) return;
@@ -96,14 +96,14 @@ vx_timer::vx_timer(vx_handle *h_, hipStream_t s_, int kind_) : h(h_), s(s_), kin
         }
         h->events.push_back(p);
     }
-    pair = &h->events[h->events_used++];
-    pair->kind = kind;
-    (void)hipEventRecord(pair->start, s);
+    slot = (int64_t)h->events_used++;
+    h->events[slot].kind = kind;
+    (void)hipEventRecord(h->events[slot].start, s);
 }
 
 void vx_timer::stop() {
-    if (pair) (void)hipEventRecord(pair->stop, s);
-    pair = nullptr;
+    if (slot >= 0) (void)hipEventRecord(h->events[slot].stop, s);
+    slot = -1;
 }
 
 extern "C" vx_status vx_profile_enable(vx_handle *h, int enable) {
