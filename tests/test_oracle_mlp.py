@@ -1,0 +1,110 @@
+"""Pins of the FP64 surrogate network of the oracle (oracle.mlp) against what mathematics fixes:
+central differences of the loss, textbook values of the normal CDF, the odd-part identity of GELU,
+Adam's closed form under a constant gradient, the feature normalisation, and bfloat16 rounding
+against an independent conversion."""
+import numpy as np
+import pytest
+
+import vxinputs
+from oracle import mlp as M
+
+
+def small_problem(seed=0, n=12):
+    rng = np.random.default_rng(seed)
+    P = vxinputs.mlp_init(seed + 7)
+    for k in ("b1", "b2", "b3"):
+        P[k] = rng.normal(0, 0.3, P[k].shape)
+    P["W3"] = P["W3"] * 10.0  # outputs of order 1 so that both confidence targets occur
+    X = rng.normal(size=(n, 128))
+    Z3 = M.forward(P, X)["Z3"]
+    T = Z3[:, :3] + rng.normal(0, 0.2, (n, 3))
+    T[: n // 2] = Z3[: n // 2, :3] + 0.005  # half the samples within the confidence tolerance
+    return P, X, T
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_gradient_central_differences(lam):
+    P, X, T = small_problem()
+    loss, G, y = M.loss_grad(P, X, T, lam=lam, tol=0.02)
+    assert 0 < y.sum() < len(y)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    for name in M.NAMES:
+        idx = [tuple(rng.integers(0, s) for s in P[name].shape) for _ in range(12)]
+        fd, an = [], []
+        for i in idx:
+            Pp = {k: v.copy() for k, v in P.items()}
+            Pm = {k: v.copy() for k, v in P.items()}
+            Pp[name][i] += h
+            Pm[name][i] -= h
+            lp = M.loss_grad(Pp, X, T, lam=lam, tol=0.02, y=y)[0]
+            lm = M.loss_grad(Pm, X, T, lam=lam, tol=0.02, y=y)[0]
+            fd.append((lp - lm) / (2 * h))
+            an.append(G[name][i])
+        fd, an = np.array(fd), np.array(an)
+        rel = np.linalg.norm(fd - an) / max(np.linalg.norm(an), 1e-300)
+        assert rel <= 1e-6, (name, rel)
+
+
+def test_gelu_values_and_identities():
+    # gelu(x) = x Phi(x); Phi(1) and Phi(2) from tables of the standard normal CDF
+    assert M.gelu(np.float64(1.0)) == pytest.approx(0.8413447460685429, abs=1e-15)
+    assert M.gelu(np.float64(2.0)) == pytest.approx(2 * 0.9772498680518208, abs=1e-15)
+    assert M.gelu(np.float64(0.0)) == 0.0
+    x = np.linspace(-6, 6, 241)
+    # Phi(x) + Phi(-x) = 1  =>  gelu(x) - gelu(-x) = x
+    assert np.abs(M.gelu(x) - M.gelu(-x) - x).max() < 1e-14
+    assert M.gelu(np.float64(40.0)) == 40.0 and abs(M.gelu(np.float64(-40.0))) < 1e-300
+    h = 1e-6
+    fd = (M.gelu(x + h) - M.gelu(x - h)) / (2 * h)
+    assert np.abs(fd - M.gelu_grad(x)).max() < 1e-8
+    assert M.gelu_grad(np.float64(0.0)) == 0.5
+
+
+def test_adam_closed_form():
+    rng = np.random.default_rng(5)
+    P = {"w": rng.normal(size=50)}
+    g = {"w": rng.normal(size=50)}
+    Mo = {"w": np.zeros(50)}
+    V = {"w": np.zeros(50)}
+    lr, eps = 1e-3, 1e-8
+    w0 = P["w"].copy()
+    for t in range(1, 6):
+        P, Mo, V = M.adam(P, g, Mo, V, t, lr, eps=eps)
+        # with a constant gradient the bias-corrected moments are exactly g and g^2
+        step = lr * g["w"] / (np.abs(g["w"]) + eps)
+        assert np.abs(P["w"] - (w0 - t * step)).max() < 1e-12
+
+
+def test_features():
+    rng = np.random.default_rng(8)
+    re, im = rng.normal(size=(4, 4, 4)), rng.normal(size=(4, 4, 4))
+    f = M.features(re, im)
+    assert f.shape == (128,)
+    assert (f * f).sum() == pytest.approx(64.0, rel=1e-12)  # mean |psi|^2 normalised to 1
+    assert np.allclose(M.features(3.7 * re, 3.7 * im), f, rtol=0, atol=1e-14)
+    th = 0.83  # a global phase rotates every (Re, Im) pair by the same angle
+    c, s = np.cos(th), np.sin(th)
+    g = M.features(c * re - s * im, s * re + c * im)
+    assert np.allclose(g[0::2], c * f[0::2] - s * f[1::2], atol=1e-13)
+    assert np.allclose(g[1::2], s * f[0::2] + c * f[1::2], atol=1e-13)
+    assert f[2 * (1 + 4 * 2 + 16 * 3)] == pytest.approx(re[3, 2, 1] / np.sqrt(np.mean(re ** 2 + im ** 2)))
+    assert not M.features(np.zeros(64), np.zeros(64)).any()
+
+
+def test_first_estimate():
+    assert np.allclose(M.first_estimate(0b01 | 0b11 << 2), [0.5, 0.5, 0.5])  # -x and +x pierced
+    assert np.allclose(M.first_estimate(0b01 | 0b11 << 6), [0.25, 0.75, 0.5])  # -x and +y
+    assert np.allclose(M.first_estimate(0b01 << 8 | 0b11 << 10), [0.5, 0.5, 0.5])  # -z and +z
+    assert np.allclose(M.first_estimate(0), [0.5, 0.5, 0.5])
+
+
+def test_bf16_rounding():
+    import torch
+    one = 1.0
+    assert M.bf16(np.array([one + 2.0 ** -8]))[0] == 1.0  # tie to even
+    assert M.bf16(np.array([one + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6  # tie to even, upwards
+    assert M.bf16(np.array([one + 2.0 ** -8 + 2.0 ** -20]))[0] == 1.0 + 2.0 ** -7
+    x = np.random.default_rng(9).normal(size=10000) * np.exp(np.random.default_rng(10).uniform(-20, 20, 10000))
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16(x), ref)

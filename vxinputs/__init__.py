@@ -235,3 +235,44 @@ def random_small_int_field(dims, seed: int, lo: int = -2, hi: int = 2) -> np.nda
     rng = np.random.default_rng(seed)
     v = rng.integers(lo, hi + 1, size=(nz, ny, nx, 2)).astype(np.float32)
     return v.view(np.complex64)[..., 0].copy()
+
+
+# ----------------------------------------------------------------------------------------------
+# Surrogate network: initial weights and the flat parameter layout
+# ----------------------------------------------------------------------------------------------
+
+MLP_SHAPES = (("W1", (128, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (256, 4)),
+              ("b3", (4,)))
+MLP_NPARAMS = sum(int(np.prod(s)) for _, s in MLP_SHAPES)
+
+
+def mlp_init(seed: int) -> dict:
+    """Random initial weights (float64): W ~ N(0, 1/fan_in) (last layer scaled by 0.1), biases 0."""
+    rng = np.random.default_rng(seed)
+    P = {}
+    for name, shape in MLP_SHAPES:
+        if name.startswith("W"):
+            scale = 1.0 / np.sqrt(shape[0]) * (0.1 if name == "W3" else 1.0)
+            P[name] = rng.normal(0.0, scale, size=shape)
+        else:
+            P[name] = np.zeros(shape)
+    return P
+
+
+def mlp_pack(P: dict) -> np.ndarray:
+    """Flat float32 vector in the library's layout: W1 (row-major, rows = inputs), b1, W2, b2, W3, b3."""
+    return np.concatenate([np.asarray(P[n], np.float64).reshape(-1) for n, _ in MLP_SHAPES]).astype(np.float32)
+
+
+def mlp_unpack(v: np.ndarray) -> dict:
+    P, o = {}, 0
+    for n, s in MLP_SHAPES:
+        k = int(np.prod(s))
+        P[n] = np.asarray(v[o:o + k], np.float64).reshape(s)
+        o += k
+    return P
+
+
+def surrogate_train_tangles(first: int = 1000, count: int = 150):
+    """Training fields: 256^3 random-wave tangles like the 256^3 case (512 waves, |n| in [4, 8])."""
+    return [make_tangle((256, 256, 256), 512, (4, 8), s) for s in range(first, first + count)]
