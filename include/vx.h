@@ -189,6 +189,85 @@ vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_
                     int64_t cap, const vx_refine_params *p, vx_sample *d_out, vx_stream s);
 
 /* ------------------------------------------------------------------------------------------
+ * Learned surrogate of the refinement (an extension of the method; the plain refinement above
+ * labels its training data, judges its error and takes over below a confidence threshold).
+ *
+ * Network: inputs f (128) from the 4x4x4 patch of nodes around a cell (offsets -1..2 on each
+ * axis from the min corner; patch node q = a + 4b + 16c, x fastest): f[2q] = Re psi_q / s,
+ * f[2q+1] = Im psi_q / s, s = sqrt(mean_q |psi_q|^2) (s = 1 if zero). Z1 = f W1 + b1,
+ * H1 = gelu(Z1), Z2 = H1 W2 + b2, H2 = gelu(Z2), Z3 = H2 W3 + b3 with W1 128x256, W2 256x256,
+ * W3 256x4 (row index = input), gelu(x) = x (1 + erf(x / sqrt 2)) / 2. Outputs: Z3[0..2] = the
+ * core sample minus the cell's first estimate x0 (mean of its pierced-face centres, cell units);
+ * conf = 1 / (1 + exp(-Z3[3])).
+ * Arithmetic: BF16 matrix operands (features, weights, activations) on the matrix cores with FP32
+ * accumulation; biases, master weights, Adam moments and the loss in FP32; gelu and its
+ * derivative read from FP32 tables of the exact function (erff/expf at creation, 1/64 spacing on
+ * [-8, 8], linear interpolation, error below 3e-5; identity / zero outside).
+ * Parameters (host layout, VX_MLP_NPARAMS floats): W1 row-major, b1, W2, b2, W3, b3.
+ * Training loss per sample: |Z3[0..2] - t|^2 + lambda * (log(1 + exp(Z3[3])) - y Z3[3]), y = 1 if
+ * the current prediction is within conf_tol of t on every axis (no gradient through y); the mean
+ * over the minibatch is minimised with Adam.
+ * ---------------------------------------------------------------------------------------- */
+#define VX_MLP_NIN 128
+#define VX_MLP_NHID 256
+#define VX_MLP_NOUT 4
+#define VX_MLP_NPARAMS 99844
+#define VX_SAMPLE_SURROGATE 128u  /* position from the surrogate network (iters = 0) */
+
+typedef struct vx_mlp vx_mlp;
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam */
+    float conf_lambda;           /* weight of the confidence loss */
+    float conf_tol;              /* prediction counted as good within this many cells per axis */
+} vx_adam_params;
+
+/* h_params: VX_MLP_NPARAMS initial values (host memory, copied). max_batch: largest minibatch of
+ * the training calls (their scratch, about 3 KiB per row, is allocated here). */
+vx_status vx_mlp_create(vx_handle *h, const float *h_params, int64_t max_batch, vx_mlp **out);
+vx_status vx_mlp_destroy(vx_mlp *m);
+/* Copy the FP32 parameters to / from host memory (synchronous). */
+vx_status vx_mlp_get_params(vx_mlp *m, float *h_params);
+vx_status vx_mlp_set_params(vx_mlp *m, const float *h_params);
+/* Save / load the parameters as a little-endian file ("VXMLP1", count, floats). */
+vx_status vx_mlp_save(vx_mlp *m, const char *path);
+vx_status vx_mlp_load(vx_mlp *m, const char *path);
+
+/* Training data from refined samples: for listed cell i < min(*d_count, cap) whose sample
+ * d_samples[i] has none of the status bits MULTI, NO_FACES, NONZERO_MIN, NOT_CONVERGED, BOUNDARY,
+ * BAD_CELL and whose patch lies inside the grid, append its features (BF16, 128 per row) to
+ * d_feat and its target (sample offset minus x0, 3 floats) to d_target. *d_n (device int64,
+ * zeroed by the caller) counts appended rows; rows beyond n_cap are counted but not stored. */
+vx_status vx_mlp_dataset(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                         const uint16_t *d_cell_desc, const vx_sample *d_samples, const int64_t *d_count,
+                         int64_t cap, uint16_t *d_feat, float *d_target, int64_t *d_n, int64_t n_cap,
+                         vx_stream s);
+/* Features of the listed cells (BF16 [n][128], n = min(*d_count, cap)); cells whose patch leaves
+ * a non-periodic grid get the clamped patch. */
+vx_status vx_mlp_features(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                          const int64_t *d_count, int64_t cap, uint16_t *d_feat, vx_stream s);
+
+/* One Adam step on the minibatch rows d_idx[0..n-1] of (d_feat, d_target) (d_idx NULL: rows
+ * 0..n-1), n <= max_batch. d_loss (nullable, 2 floats) receives the batch's mean squared error
+ * and mean confidence loss. */
+vx_status vx_mlp_train_step(vx_mlp *m, const uint16_t *d_feat, const float *d_target, const int32_t *d_idx,
+                            int64_t n, const vx_adam_params *p, float *d_loss, vx_stream s);
+/* Gradient of the mean loss on rows 0..n-1 into d_grad (VX_MLP_NPARAMS floats, host layout),
+ * without updating the parameters. */
+vx_status vx_mlp_grad(vx_mlp *m, const uint16_t *d_feat, const float *d_target, int64_t n, float conf_lambda,
+                      float conf_tol, float *d_grad, float *d_loss, vx_stream s);
+/* Network outputs for rows 0..n-1: d_out[n][4] = (Z3[0], Z3[1], Z3[2], conf). */
+vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n, float *d_out, vx_stream s);
+
+/* Core samples of the listed cells (as vx_refine) through the surrogate: a cell gets the
+ * network's position x0 + Z3[0..2] (status VX_SAMPLE_SURROGATE, rho = |trilinear psi|^2 there,
+ * iters 0) when conf >= conf_threshold, its first estimate has two pierced faces and its patch lies
+ * inside the grid; every other cell is refined by the plain method with p (NULL = defaults),
+ * exactly as vx_refine would. No host synchronisation. */
+vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                       const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
+                       const vx_refine_params *p, vx_sample *d_out, vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
  * Batching: winding + compaction and refinement of many grids of uneven size (a time series of
  * frames, Sec. 5 timing over time steps) in one captured HIP graph.
  *

@@ -31,7 +31,13 @@ KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH = 0, 1, 2, 3
 EXPORTS = ["vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
-           "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_profile_enable", "vx_profile_read"]
+           "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
+           "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
+           "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_infer",
+           "vx_profile_enable", "vx_profile_read"]
+
+MLP_NPARAMS = 99844
+SAMPLE_SURROGATE = 128
 
 BATCH_MAX_FRAMES = 128
 
@@ -76,6 +82,10 @@ class Sample(ctypes.Structure):
 
 
 assert ctypes.sizeof(Sample) == 32
+
+
+class AdamParams(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("lr", "beta1", "beta2", "eps", "conf_lambda", "conf_tol")]
 
 
 class Frame(ctypes.Structure):
@@ -131,6 +141,23 @@ def lib() -> ctypes.CDLL:
         L.vx_batch_destroy.restype = st
         L.vx_autotune.argtypes = [P, Dims, P, ctypes.c_char_p, ctypes.POINTER(i), P]
         L.vx_autotune.restype = st
+        i64, f = ctypes.c_int64, ctypes.c_float
+        L.vx_mlp_create.argtypes = [P, P, i64, ctypes.POINTER(P)]
+        L.vx_mlp_destroy.argtypes = [P]
+        L.vx_mlp_get_params.argtypes = [P, P]
+        L.vx_mlp_set_params.argtypes = [P, P]
+        L.vx_mlp_save.argtypes = [P, ctypes.c_char_p]
+        L.vx_mlp_load.argtypes = [P, ctypes.c_char_p]
+        L.vx_mlp_dataset.argtypes = [P, Dims, P, P, P, P, P, i64, P, P, P, i64, P]
+        L.vx_mlp_features.argtypes = [P, Dims, P, P, P, i64, P, P]
+        L.vx_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.POINTER(AdamParams), P, P]
+        L.vx_mlp_grad.argtypes = [P, P, P, i64, f, f, P, P, P]
+        L.vx_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.vx_mlp_infer.argtypes = [P, Dims, P, P, P, P, i64, f, ctypes.POINTER(RefineParams), P, P]
+        for name in ("vx_mlp_create", "vx_mlp_destroy", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save",
+                     "vx_mlp_load", "vx_mlp_dataset", "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad",
+                     "vx_mlp_forward", "vx_mlp_infer"):
+            getattr(L, name).restype = st
         L.vx_profile_enable.argtypes = [P, i]
         L.vx_profile_enable.restype = st
         L.vx_profile_read.argtypes = [P, i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -263,6 +290,79 @@ def vx_autotune(h, d: Dims, psi, cache_path: str | None = None, stream=None) -> 
     path = cache_path.encode() if cache_path else None
     _check(h, lib().vx_autotune(h, d, _ptr(psi), path, ctypes.byref(z), _stream(stream)), "vx_autotune")
     return z.value
+
+
+# ---------------------------------------------------------------------------------------------- surrogate
+def _host_f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != MLP_NPARAMS:
+        raise ValueError(f"expected {MLP_NPARAMS} parameters, got {a.size}")
+    return a
+
+
+def vx_mlp_create(h, params, max_batch: int):
+    a = _host_f32(params)
+    m = ctypes.c_void_p()
+    _check(h, lib().vx_mlp_create(h, a.ctypes.data, int(max_batch), ctypes.byref(m)), "vx_mlp_create")
+    return m
+
+
+def vx_mlp_destroy(h, m):
+    _check(h, lib().vx_mlp_destroy(m), "vx_mlp_destroy")
+
+
+def vx_mlp_get_params(h, m):
+    import numpy as np
+    a = np.empty(MLP_NPARAMS, np.float32)
+    _check(h, lib().vx_mlp_get_params(m, a.ctypes.data), "vx_mlp_get_params")
+    return a
+
+
+def vx_mlp_set_params(h, m, params):
+    a = _host_f32(params)
+    _check(h, lib().vx_mlp_set_params(m, a.ctypes.data), "vx_mlp_set_params")
+
+
+def vx_mlp_save(h, m, path: str):
+    _check(h, lib().vx_mlp_save(m, path.encode()), "vx_mlp_save")
+
+
+def vx_mlp_load(h, m, path: str):
+    _check(h, lib().vx_mlp_load(m, path.encode()), "vx_mlp_load")
+
+
+def vx_mlp_dataset(h, d: Dims, psi, cells, cdesc, samples, count, cap, feat, target, n_out, n_cap, stream=None):
+    _check(h, lib().vx_mlp_dataset(h, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(samples), _ptr(count), int(cap),
+                                   _ptr(feat), _ptr(target), _ptr(n_out), int(n_cap), _stream(stream)),
+           "vx_mlp_dataset")
+
+
+def vx_mlp_features(h, d: Dims, psi, cells, count, cap, feat, stream=None):
+    _check(h, lib().vx_mlp_features(h, d, _ptr(psi), _ptr(cells), _ptr(count), int(cap), _ptr(feat),
+                                    _stream(stream)), "vx_mlp_features")
+
+
+def vx_mlp_train_step(h, m, feat, target, idx, n: int, adam: AdamParams, loss=None, stream=None):
+    _check(h, lib().vx_mlp_train_step(m, _ptr(feat), _ptr(target), _ptr(idx), int(n), ctypes.byref(adam), _ptr(loss),
+                                      _stream(stream)), "vx_mlp_train_step")
+
+
+def vx_mlp_grad(h, m, feat, target, n: int, conf_lambda: float, conf_tol: float, grad, loss=None, stream=None):
+    _check(h, lib().vx_mlp_grad(m, _ptr(feat), _ptr(target), int(n), float(conf_lambda), float(conf_tol), _ptr(grad),
+                                _ptr(loss), _stream(stream)), "vx_mlp_grad")
+
+
+def vx_mlp_forward(h, m, feat, n: int, out, stream=None):
+    _check(h, lib().vx_mlp_forward(m, _ptr(feat), int(n), _ptr(out), _stream(stream)), "vx_mlp_forward")
+
+
+def vx_mlp_infer(h, m, d: Dims, psi, cells, cdesc, count, cap, conf_threshold: float, out,
+                 params: RefineParams | None = None, stream=None):
+    prm = params if params is not None else vx_refine_defaults()
+    _check(h, lib().vx_mlp_infer(m, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(count), int(cap),
+                                 float(conf_threshold), ctypes.byref(prm), _ptr(out), _stream(stream)),
+           "vx_mlp_infer")
 
 
 def vx_profile_enable(h, enable: bool = True):

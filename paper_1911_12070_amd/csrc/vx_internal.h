@@ -91,9 +91,11 @@ vx_status vx_check_refine_params(vx_handle *h, const vx_refine_params &p);
 // kernels (one translation unit each)
 vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const vx_winding_out &o,
                          hipStream_t s);
+// out_index (nullable): sample s of the list goes to out[out_index[s]]
 vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
                            const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
-                           const vx_refine_params &p, vx_sample *out, hipStream_t s);
+                           const vx_refine_params &p, vx_sample *out, hipStream_t s,
+                           const int64_t *out_index = nullptr);
 
 // winding arguments of one grid with a given z-chunk depth (0 = the handle's choice); *ntiles
 // receives the number of tiles (workgroups)

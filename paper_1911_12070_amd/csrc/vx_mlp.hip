@@ -1,0 +1,1024 @@
+// Surrogate of the core-sample refinement: a 128-256-256-4 GELU network that maps the 4x4x4 psi
+// patch of a pierced cell to the offset of its refined core sample from the first estimate (the
+// mean of the pierced-face centres, Sec. 3.3.1) plus a confidence. Training data are produced by
+// the plain refinement (Sec. 3.3.3); below the confidence threshold the plain refinement runs.
+//
+// Matrix cores. The two hidden layers are BF16 products with FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16: lane l of a wavefront holds row (l % 16) of a 16x32 A block and column
+// (l % 16) of a 32x16 B block, k = 8 (l / 16) .. +7 as eight BF16 values; the 16x16 FP32 result
+// holds rows 4 (l / 16) + i, column l % 16 in its four registers. A workgroup (4 wavefronts) owns a
+// tile of 64 rows; wavefront w computes columns 64w .. 64w+63 of a layer for all 64 rows (4 x 4
+// blocks). A operands come from LDS (row pitch padded by 8 values so that the 16 rows of a block
+// fall on different banks), B operands are read as 16-byte vectors from transposed BF16 weight
+// copies (k contiguous), which stay in L2.
+// The 4-wide head runs on the matrix cores too (N padded to 16); its gradients, the bias
+// gradients and the loss are small reductions done on the vector ALUs.
+//
+// Training on a minibatch of n rows (all on the device, no host synchronisation):
+//   fwd_train_k   per 64-row tile: layers, H1/H2 and gelu'(Z1)/gelu'(Z2) to global scratch (BF16),
+//                 head, loss terms, dZ3 (FP32)
+//   bwd_rows_k    per tile: dZ2 = (dZ3 W3^T) * gelu'(Z2), dZ1 = (dZ2 W2^T) * gelu'(Z1) (MFMA), the
+//                 gradients of W3 and of every bias (atomics into the FP32 gradient buffer)
+//   wgrad_k       dW1 = X^T dZ1 and dW2 = H1^T dZ2: split over row chunks; each 32-row step is
+//                 staged transposed in LDS so that both operands are read as 16-byte vectors;
+//                 partial 128x128 blocks are added atomically
+//   adam_k        Adam update of the FP32 master weights, refreshed BF16 copies, gradient zeroed
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vx_internal.h"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int NIN = VX_MLP_NIN, NH = VX_MLP_NHID, NOUT = VX_MLP_NOUT;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH;
+constexpr int OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NOUT, NPARAM = OFF_B3 + NOUT;
+static_assert(NPARAM == VX_MLP_NPARAMS, "parameter count");
+
+constexpr int TM = 64;           // rows per tile
+constexpr int NT = 256;          // threads per workgroup
+constexpr int XP = NIN + 8;      // LDS row pitch (values) of the input tile
+constexpr int HP = NH + 8;       // LDS row pitch of a hidden tile
+constexpr int GT = 1024;         // table intervals on [-8, 8]
+constexpr float GLO = -8.f, GHI = 8.f, GSC = 64.f;
+constexpr int WCH = 512;         // rows per chunk of the weight-gradient kernel
+
+__device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 ld8(const __bf16 *p) { return *(const bf16x8 *)p; }
+
+// gelu (kind 0) or its derivative (kind 1) from a table of (value, next - value) at GLO + i / GSC
+__device__ __forceinline__ float tab(const float2 *t, float x, int kind) {
+    if (x >= GHI) return kind ? 1.f : x;
+    if (x <= GLO) return 0.f;
+    const float u = (x - GLO) * GSC;
+    const int i = min((int)u, GT - 1);
+    const float2 e = t[i];
+    return e.x + (u - (float)i) * e.y;
+}
+
+struct Geo {
+    const float2 *psi;
+    int nx, ny, nz, px, py, pz;
+};
+
+__device__ __forceinline__ int wrapc(int q, int n, int per) {
+    if (q < 0) return per ? q + n : 0;
+    if (q >= n) return per ? q - n : n - 1;
+    return q;
+}
+
+// cell id -> node coordinates (cells of any grid that fits in memory, < 2^53)
+__device__ __forceinline__ void cell_xyz(uint64_t cell, const Geo &g, int &i, int &j, int &k) {
+    const uint64_t nxy = (uint64_t)g.nx * (uint64_t)g.ny;
+    uint64_t q = (uint64_t)((double)cell / (double)nxy);
+    int64_t r = (int64_t)(cell - q * nxy);
+    if (r < 0) {
+        --q;
+        r += (int64_t)nxy;
+    } else if (r >= (int64_t)nxy) {
+        ++q;
+        r -= (int64_t)nxy;
+    }
+    k = (int)q;
+    j = (int)(r / g.nx);
+    i = (int)(r - (int64_t)j * g.nx);
+}
+
+// the patch lies inside the grid (always on periodic axes)
+__device__ __forceinline__ bool interior(const Geo &g, int i, int j, int k) {
+    return (g.px || (i >= 1 && i + 2 < g.nx)) && (g.py || (j >= 1 && j + 2 < g.ny)) &&
+           (g.pz || (k >= 1 && k + 2 < g.nz));
+}
+
+// Four consecutive lanes gather one patch: lane quarter c loads the 16 nodes of patch plane c and
+// the group reduces the sum of |psi|^2 with two xor shuffles (all four lanes must be active).
+// Writes the 32 BF16 features of plane c to dst[32 c .. 32 c + 31] if `write`.
+__device__ __forceinline__ void gather_features(const Geo &g, int i, int j, int k, int c, __bf16 *dst,
+                                                bool write = true) {
+    float2 v[16];
+    const int kk = wrapc(k + c - 1, g.nz, g.pz);
+    const uint64_t nx = (uint64_t)g.nx;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int jj = wrapc(j + b - 1, g.ny, g.py);
+        const float2 *row = g.psi + nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
+    }
+    float ss = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ss += v[q].x * v[q].x + v[q].y * v[q].y;
+    ss += __shfl_xor(ss, 1);
+    ss += __shfl_xor(ss, 2);
+    const float s = ss > 0.f ? sqrtf(ss * (1.f / 64.f)) : 1.f;
+    const float is = 1.f / s;
+    if (!write) return;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        dst[32 * c + 2 * q] = (__bf16)(v[q].x * is);
+        dst[32 * c + 2 * q + 1] = (__bf16)(v[q].y * is);
+    }
+}
+
+__device__ __forceinline__ void first_estimate(uint32_t desc, float &x, float &y, float &z, int &n) {
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    n = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (((desc >> (2 * f)) & 3u) == 0) continue;
+        const int a = f >> 1;
+        const float side = (float)(f & 1);
+        sx += a == 0 ? side : 0.5f;
+        sy += a == 1 ? side : 0.5f;
+        sz += a == 2 ? side : 0.5f;
+        ++n;
+    }
+    if (n == 0) {
+        x = y = z = 0.5f;
+    } else {
+        const float inv = 1.0f / (float)n;
+        x = sx * inv;
+        y = sy * inv;
+        z = sz * inv;
+    }
+}
+
+// ---------------------------------------------------------------------------- layer building blocks
+
+// acc = A (64 x K, LDS, pitch AP) times B (K x 64: columns n0 .. n0+63 of a K-contiguous weight
+// copy Wt[col][k]) for this wavefront
+template <int K, int AP>
+__device__ __forceinline__ void layer(const __bf16 *sA, const __bf16 *__restrict__ Wt, int n0, f32x4 acc[4][4]) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 b[4], a[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = ld8(Wt + (size_t)(n0 + 16 * c + (l & 15)) * K + k0 + 8 * (l >> 4));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = ld8(sA + (16 * r + (l & 15)) * AP + k0 + 8 * (l >> 4));
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+    }
+}
+
+// head: rows 16w .. 16w+15 of H (LDS) times W3 (16 x 256 padded copy); returns this lane's column
+// (l % 16) for rows 16w + 4 (l / 16) + i
+__device__ __forceinline__ f32x4 head(const __bf16 *sH, const __bf16 *__restrict__ W3t) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k0 = 0; k0 < NH; k0 += 32) {
+        const bf16x8 a = ld8(sH + (16 * w + (l & 15)) * HP + k0 + 8 * (l >> 4));
+        const bf16x8 b = ld8(W3t + (l & 15) * NH + k0 + 8 * (l >> 4));
+        acc = mfma(a, b, acc);
+    }
+    return acc;
+}
+
+struct Net {  // device copies used by the kernels
+    const float *master;  // FP32 parameters (host layout)
+    const __bf16 *w1t;    // [256][128]  W1 transposed
+    const __bf16 *w2t;    // [256][256]  W2 transposed
+    const __bf16 *w2c;    // [256][256]  W2 as is (rows = inputs): B operand of dH1 = dZ2 W2^T
+    const __bf16 *w3t;    // [16][256]   W3 transposed, rows 4..15 zero
+    const float2 *gelu;   // [GT] (value, step)
+    const float2 *dgelu;  // [GT] (derivative, step)
+};
+
+// copy the two tables into LDS (all threads)
+__device__ __forceinline__ void load_tables(const Net &N, float2 *sg, float2 *sd) {
+    for (int i = threadIdx.x; i < GT; i += NT) {
+        sg[i] = N.gelu[i];
+        if (sd) sd[i] = N.dgelu[i];
+    }
+}
+
+// both hidden layers for the input tile sX; H2 ends in sH. Optionally stores H1/H2 and the gelu
+// derivatives of the valid rows to global memory (training).
+__device__ __forceinline__ void hidden(const Net &N, const __bf16 *sX, __bf16 *sH, const float2 *sg, const float2 *sd,
+                                       int64_t row0, int64_t nrows, __bf16 *H1, __bf16 *G1, __bf16 *H2, __bf16 *G2) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n0 = 64 * w;
+    f32x4 acc[4][4];
+    layer<NIN, XP>(sX, N.w1t, n0, acc);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = n0 + 16 * c + (l & 15);
+        const float bias = N.master[OFF_B1 + col];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * r + 4 * (l >> 4) + i;
+                const float z = acc[r][c][i] + bias;
+                const __bf16 hv = (__bf16)tab(sg, z, 0);
+                sH[row * HP + col] = hv;
+                if (H1 && row0 + row < nrows) {
+                    H1[(row0 + row) * NH + col] = hv;
+                    G1[(row0 + row) * NH + col] = (__bf16)tab(sd, z, 1);
+                }
+            }
+    }
+    __syncthreads();
+    layer<NH, HP>(sH, N.w2t, n0, acc);
+    __syncthreads();  // every wavefront has read H1
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = n0 + 16 * c + (l & 15);
+        const float bias = N.master[OFF_B2 + col];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * r + 4 * (l >> 4) + i;
+                const float z = acc[r][c][i] + bias;
+                const __bf16 hv = (__bf16)tab(sg, z, 0);
+                sH[row * HP + col] = hv;
+                if (H2 && row0 + row < nrows) {
+                    H2[(row0 + row) * NH + col] = hv;
+                    G2[(row0 + row) * NH + col] = (__bf16)tab(sd, z, 1);
+                }
+            }
+    }
+    __syncthreads();
+}
+
+// network outputs of the 64 rows into sOut[64][4] (Z3 with the bias; column 3 is the logit)
+__device__ __forceinline__ void outputs(const Net &N, const __bf16 *sH, float *sOut) {
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const f32x4 z = head(sH, N.w3t);
+    const int col = l & 15;
+    if (col < NOUT) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sOut[(16 * w + 4 * (l >> 4) + i) * NOUT + col] = z[i] + N.master[OFF_B3 + col];
+    }
+    __syncthreads();
+}
+
+// load rows of BF16 features (optionally through an index list) into sX; rows past n are zero
+__device__ __forceinline__ void load_x(const __bf16 *__restrict__ feat, const int32_t *__restrict__ idx, int64_t row0,
+                                       int64_t n, __bf16 *sX) {
+    for (int e = threadIdx.x; e < TM * (NIN / 8); e += NT) {
+        const int r = e / (NIN / 8), q = e % (NIN / 8);
+        bf16x8 v;
+        if (row0 + r < n) {
+            const int64_t src = idx ? (int64_t)idx[row0 + r] : row0 + r;
+            v = ld8(feat + src * NIN + 8 * q);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.f;
+        }
+        *(bf16x8 *)(sX + r * XP + 8 * q) = v;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------- kernels
+
+__global__ void tables_k(float2 *gelu, float2 *dgelu) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= GT) return;
+    auto g = [](double x) { return x * 0.5 * (1.0 + erf(x / sqrt(2.0))); };
+    auto dg = [](double x) { return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * M_PI); };
+    const double x0 = GLO + (double)i / GSC, x1 = GLO + (double)(i + 1) / GSC;
+    gelu[i] = make_float2((float)g(x0), (float)(g(x1) - g(x0)));
+    dgelu[i] = make_float2((float)dg(x0), (float)(dg(x1) - dg(x0)));
+}
+
+// host-layout FP32 parameters -> BF16 operand copies
+__global__ void refresh_k(const float *__restrict__ p, __bf16 *w1t, __bf16 *w2t, __bf16 *w2c, __bf16 *w3t) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < OFF_B3; e += gridDim.x * blockDim.x) {
+        const __bf16 v = (__bf16)p[e];
+        if (e < OFF_B1) {
+            const int i = e / NH, o = e % NH;
+            w1t[o * NIN + i] = v;
+        } else if (e >= OFF_W2 && e < OFF_B2) {
+            const int q = e - OFF_W2, i = q / NH, o = q % NH;
+            w2t[o * NH + i] = v;
+            w2c[q] = v;
+        } else if (e >= OFF_W3) {
+            const int q = e - OFF_W3, i = q / NOUT, o = q % NOUT;
+            w3t[o * NH + i] = v;
+        }
+    }
+}
+
+// forward of a minibatch with everything the backward pass needs; loss terms and dZ3
+__global__ __launch_bounds__(NT) void fwd_train_k(Net N, const __bf16 *__restrict__ feat, const float *__restrict__ target,
+                                                  const int32_t *__restrict__ idx, int64_t n, float lam, float tol,
+                                                  __bf16 *H1, __bf16 *G1, __bf16 *H2, __bf16 *G2, float *dZ3,
+                                                  float *loss) {
+    __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
+    __shared__ float2 sg[GT], sd[GT];
+    __shared__ float sOut[TM * NOUT];
+    const int64_t row0 = (int64_t)blockIdx.x * TM;
+    load_tables(N, sg, sd);
+    load_x(feat, idx, row0, n, sX);
+    hidden(N, sX, sH, sg, sd, row0, n, H1, G1, H2, G2);
+    outputs(N, sH, sOut);
+    // loss terms of the tile's rows (one thread per row), reduced over the wavefront
+    const int t = threadIdx.x;
+    float mse = 0.f, bce = 0.f;
+    if (t < TM && row0 + t < n) {
+        const int64_t r = row0 + t;
+        const int64_t src = idx ? (int64_t)idx[r] : r;
+        const float inv_n = 1.f / (float)n;
+        float d[3], dm = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            d[a] = sOut[t * NOUT + a] - target[src * 3 + a];
+            mse += d[a] * d[a];
+            dm = fmaxf(dm, fabsf(d[a]));
+        }
+        const float z = sOut[t * NOUT + 3];
+        const float y = dm < tol ? 1.f : 0.f;
+        bce = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - y * z;
+        const float sg_ = 1.f / (1.f + expf(-z));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dZ3[r * NOUT + a] = 2.f * d[a] * inv_n;
+        dZ3[r * NOUT + 3] = lam * (sg_ - y) * inv_n;
+    }
+    if (t < 64) {
+        for (int o = 32; o > 0; o >>= 1) {
+            mse += __shfl_xor(mse, o);
+            bce += __shfl_xor(bce, o);
+        }
+        if (t == 0 && loss) {
+            atomicAdd(&loss[0], mse / (float)n);
+            atomicAdd(&loss[1], bce / (float)n);
+        }
+    }
+}
+
+// backward through the layers for a 64-row tile: dZ2, dZ1 (global), gradients of W3 and the biases
+__global__ __launch_bounds__(NT) void bwd_rows_k(Net N, int64_t n, const float *__restrict__ dZ3,
+                                                 const __bf16 *__restrict__ H2, const __bf16 *__restrict__ G1,
+                                                 const __bf16 *__restrict__ G2, __bf16 *dZ2g, __bf16 *dZ1g,
+                                                 float *grad) {
+    __shared__ __attribute__((aligned(16))) __bf16 sD[TM * HP];  // dZ2 tile (A operand)
+    __shared__ float sZ3[TM * NOUT];
+    __shared__ float sW3[NH * NOUT];
+    const int t = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * TM;
+    for (int e = t; e < TM * NOUT; e += NT) sZ3[e] = row0 + e / NOUT < n ? dZ3[row0 * NOUT + e] : 0.f;
+    for (int e = t; e < NH * NOUT; e += NT) sW3[e] = N.master[OFF_W3 + e];
+    __syncthreads();
+    // column t: dH2 = dZ3 W3^T, dZ2 = dH2 gelu'(Z2); gradients of b2, W3 row t; b3
+    {
+        const int o = t;
+        float db2 = 0.f, gw[NOUT] = {0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < TM; ++r) {
+            float v = 0.f;
+            if (row0 + r < n) {
+                float dh = 0.f;
+#pragma unroll
+                for (int j = 0; j < NOUT; ++j) dh += sZ3[r * NOUT + j] * sW3[o * NOUT + j];
+                v = dh * (float)G2[(row0 + r) * NH + o];
+                const float h2 = (float)H2[(row0 + r) * NH + o];
+#pragma unroll
+                for (int j = 0; j < NOUT; ++j) gw[j] += h2 * sZ3[r * NOUT + j];
+            }
+            const __bf16 vb = (__bf16)v;
+            sD[r * HP + o] = vb;
+            if (row0 + r < n) dZ2g[(row0 + r) * NH + o] = vb;
+            db2 += (float)vb;
+        }
+        atomicAdd(&grad[OFF_B2 + o], db2);
+#pragma unroll
+        for (int j = 0; j < NOUT; ++j) atomicAdd(&grad[OFF_W3 + o * NOUT + j], gw[j]);
+        if (t < NOUT) {
+            float s = 0.f;
+            for (int r = 0; r < TM; ++r) s += sZ3[r * NOUT + t];
+            atomicAdd(&grad[OFF_B3 + t], s);
+        }
+    }
+    __syncthreads();
+    // dH1 = dZ2 W2^T on the matrix cores; dZ1 = dH1 gelu'(Z1); gradient of b1
+    const int l = t & 63, w = t >> 6, n0 = 64 * w;
+    f32x4 acc[4][4];
+    layer<NH, HP>(sD, N.w2c, n0, acc);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int col = n0 + 16 * c + (l & 15);
+        float db1 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * r + 4 * (l >> 4) + i;
+                if (row0 + row < n) {
+                    const __bf16 v = (__bf16)(acc[r][c][i] * (float)G1[(row0 + row) * NH + col]);
+                    dZ1g[(row0 + row) * NH + col] = v;
+                    db1 += (float)v;
+                }
+            }
+        db1 += __shfl_xor(db1, 16);
+        db1 += __shfl_xor(db1, 32);
+        if (l < 16) atomicAdd(&grad[OFF_B1 + col], db1);
+    }
+}
+
+// C[M][N] += sum over rows r of A[r][M] B[r][N]: A, B row-major BF16 with leading dimensions MA,
+// NB (A rows optionally through idx); block (chunk, mt, nt) covers rows [chunk*WCH, +WCH) and the
+// 128x128 output block (mt, nt); each 32-row step is staged transposed in LDS.
+__global__ __launch_bounds__(NT) void wgrad_k(const __bf16 *__restrict__ A, int MA, const int32_t *__restrict__ idx,
+                                              const __bf16 *__restrict__ B, int NB, int64_t n, float *C) {
+    constexpr int KP = 40;  // LDS pitch of a transposed 32-row step
+    __shared__ __attribute__((aligned(16))) __bf16 sA[128 * KP];
+    __shared__ __attribute__((aligned(16))) __bf16 sB[128 * KP];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int m0 = 128 * blockIdx.y, nb0 = 128 * blockIdx.z;
+    const int64_t r0 = (int64_t)blockIdx.x * WCH;
+    const int64_t r1 = min(n, r0 + WCH);
+    const int wm = 64 * (w & 1), wn = 64 * (w >> 1);
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = r0; k0 < r1; k0 += 32) {
+        // thread t stages row (t / 8) of the step, 16 columns (t % 8) * 16 .. +15 of each operand
+        {
+            const int rr = t >> 3, cc = (t & 7) * 16;
+            const int64_t r = k0 + rr;
+            bf16x8 a0, a1, b0, b1;
+            if (r < r1) {
+                const int64_t ra = idx ? (int64_t)idx[r] : r;
+                a0 = ld8(A + ra * MA + m0 + cc);
+                a1 = ld8(A + ra * MA + m0 + cc + 8);
+                b0 = ld8(B + r * NB + nb0 + cc);
+                b1 = ld8(B + r * NB + nb0 + cc + 8);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a0[j] = a1[j] = b0[j] = b1[j] = (__bf16)0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sA[(cc + j) * KP + rr] = a0[j];
+                sA[(cc + 8 + j) * KP + rr] = a1[j];
+                sB[(cc + j) * KP + rr] = b0[j];
+                sB[(cc + 8 + j) * KP + rr] = b1[j];
+            }
+        }
+        __syncthreads();
+        bf16x8 a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = ld8(sA + (wm + 16 * r + (l & 15)) * KP + 8 * (l >> 4));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = ld8(sB + (wn + 16 * c + (l & 15)) * KP + 8 * (l >> 4));
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = m0 + wm + 16 * r + 4 * (l >> 4) + i;
+                const int nn = nb0 + wn + 16 * c + (l & 15);
+                atomicAdd(&C[(size_t)m * NB + nn], acc[r][c][i]);
+            }
+}
+
+__global__ void adam_k(float *p, float *m, float *v, float *g, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NPARAM; e += gridDim.x * blockDim.x) {
+        const float ge = g[e];
+        const float me = b1 * m[e] + (1.f - b1) * ge;
+        const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
+        m[e] = me;
+        v[e] = ve;
+        p[e] -= lr * (me * c1) / (sqrtf(ve * c2) + eps);
+        g[e] = 0.f;
+    }
+}
+
+__global__ void copy_zero_k(float *g, float *out) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < NPARAM; e += gridDim.x * blockDim.x) {
+        out[e] = g[e];
+        g[e] = 0.f;
+    }
+}
+
+__global__ void zero_f_k(float *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.f;
+}
+
+// plain forward: outputs (Z3[0..2], conf) of feature rows
+__global__ __launch_bounds__(NT) void fwd_k(Net N, const __bf16 *__restrict__ feat, int64_t n, float *out) {
+    __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
+    __shared__ float2 sg[GT];
+    __shared__ float sOut[TM * NOUT];
+    const int64_t row0 = (int64_t)blockIdx.x * TM;
+    load_tables(N, sg, nullptr);
+    load_x(feat, nullptr, row0, n, sX);
+    hidden(N, sX, sH, sg, nullptr, row0, n, nullptr, nullptr, nullptr, nullptr);
+    outputs(N, sH, sOut);
+    const int t = threadIdx.x;
+    if (t < TM && row0 + t < n) {
+        out[(row0 + t) * 4 + 0] = sOut[t * NOUT + 0];
+        out[(row0 + t) * 4 + 1] = sOut[t * NOUT + 1];
+        out[(row0 + t) * 4 + 2] = sOut[t * NOUT + 2];
+        out[(row0 + t) * 4 + 3] = 1.f / (1.f + expf(-sOut[t * NOUT + 3]));
+    }
+}
+
+// features of listed cells, four lanes per cell (64 cells per workgroup)
+__global__ __launch_bounds__(NT) void features_k(Geo g, const uint64_t *__restrict__ cells,
+                                                 const int64_t *__restrict__ count, int64_t cap, __bf16 *feat) {
+    const int64_t n = min(*count, cap);
+    const int64_t s = (int64_t)blockIdx.x * TM + (threadIdx.x >> 2);
+    const int c = threadIdx.x & 3;
+    const bool ok = s < n;
+    const uint64_t cell = ok ? cells[s] : 0;
+    const uint64_t ncell = (uint64_t)g.nx * g.ny * g.nz;
+    int i = 0, j = 0, k = 0;
+    if (cell < ncell) cell_xyz(cell, g, i, j, k);
+    gather_features(g, i, j, k, c, feat + (ok ? s : 0) * NIN, ok);
+}
+
+// training rows from refined samples (see vx_mlp_dataset)
+__global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restrict__ cells, const uint16_t *__restrict__ desc,
+                                                const vx_sample *__restrict__ smp, const int64_t *__restrict__ count,
+                                                int64_t cap, __bf16 *feat, float *target, unsigned long long *d_n,
+                                                int64_t n_cap) {
+    const int64_t n = min(*count, cap);
+    const int64_t s = (int64_t)blockIdx.x * TM + (threadIdx.x >> 2);
+    const int c = threadIdx.x & 3;
+    const uint32_t bad = VX_SAMPLE_MULTI | VX_SAMPLE_NO_FACES | VX_SAMPLE_NONZERO_MIN | VX_SAMPLE_NOT_CONVERGED |
+                         VX_SAMPLE_BOUNDARY | VX_SAMPLE_BAD_CELL;
+    bool keep = false;
+    uint64_t cell = 0;
+    int i = 0, j = 0, k = 0;
+    if (s < n) {
+        cell = cells[s];
+        keep = (smp[s].status & bad) == 0 && smp[s].cell == cell && cell < (uint64_t)g.nx * g.ny * g.nz;
+        if (keep) {
+            cell_xyz(cell, g, i, j, k);
+            keep = interior(g, i, j, k);
+        }
+    }
+    // one slot per kept cell: the group's first lane reserves it, the others read it by shuffle
+    unsigned long long slot = 0;
+    if (keep && c == 0) slot = atomicAdd(d_n, 1ull);
+    const int lead = (int)(threadIdx.x & ~3u) & 63;
+    slot = ((unsigned long long)(uint32_t)__shfl((int)(slot >> 32), lead) << 32) | (uint32_t)__shfl((int)slot, lead);
+    const bool store = keep && (int64_t)slot < n_cap;
+    gather_features(g, i, j, k, c, feat + (store ? (int64_t)slot : 0) * NIN, store);
+    if (store) {
+        if (c == 0) {
+            float x0, y0, z0;
+            int np;
+            first_estimate(desc[s], x0, y0, z0, np);
+            target[slot * 3 + 0] = smp[s].off[0] - x0;
+            target[slot * 3 + 1] = smp[s].off[1] - y0;
+            target[slot * 3 + 2] = smp[s].off[2] - z0;
+        }
+    }
+}
+
+// Inference: 64 listed cells per workgroup. Confident single-core interior cells get the network's
+// sample; the others are queued (cell, descriptor, position in the list) for the plain refinement.
+__global__ __launch_bounds__(NT) void infer_k(Net N, Geo g, const uint64_t *__restrict__ cells,
+                                              const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
+                                              int64_t cap, float thr, vx_sample *out, uint64_t *fb_cell,
+                                              uint16_t *fb_desc, int64_t *fb_index, int64_t *fb_count) {
+    __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
+    __shared__ float2 sg[GT];
+    __shared__ float sOut[TM * NOUT];
+    __shared__ int sUse[TM];
+    const int64_t n = min(*count, cap);
+    const int64_t row0 = (int64_t)blockIdx.x * TM;
+    if (row0 >= n) return;  // uniform per workgroup
+    const int t = threadIdx.x;
+    load_tables(N, sg, nullptr);
+    {
+        const int r = t >> 2, c = t & 3;
+        const int64_t s = row0 + r;
+        uint64_t cell = s < n ? cells[s] : 0;
+        const uint64_t ncell = (uint64_t)g.nx * g.ny * g.nz;
+        int i = 0, j = 0, k = 0;
+        bool use = s < n && cell < ncell;
+        if (use) {
+            cell_xyz(cell, g, i, j, k);
+            use = interior(g, i, j, k);
+        }
+        gather_features(g, i, j, k, c, sX + r * XP);
+        if (c == 0) sUse[r] = use ? 1 : 0;
+    }
+    __syncthreads();
+    hidden(N, sX, sH, sg, nullptr, row0, n, nullptr, nullptr, nullptr, nullptr);
+    outputs(N, sH, sOut);
+    if (t < 64) {
+        const int64_t s = row0 + t;
+        bool mine = false, queue = false;
+        uint64_t cell = 0;
+        uint32_t d = 0;
+        vx_sample o{};
+        if (s < n) {
+            cell = cells[s];
+            d = desc[s];
+            float x0, y0, z0;
+            int np;
+            first_estimate(d, x0, y0, z0, np);
+            const float conf = 1.f / (1.f + expf(-sOut[t * NOUT + 3]));
+            mine = sUse[t] && np == 2 && conf >= thr;
+            queue = !mine;
+            if (mine) {
+                const float x = x0 + sOut[t * NOUT + 0], y = y0 + sOut[t * NOUT + 1], z = z0 + sOut[t * NOUT + 2];
+                // |psi|^2 of the trilinear interpolant at the sample (cell of the patch that holds it)
+                int i, j, k;
+                cell_xyz(cell, g, i, j, k);
+                const float xs[3] = {x, y, z};
+                int cl[3];
+                float u[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    int f = (int)floorf(xs[a]);
+                    f = max(-1, min(f, 1));
+                    cl[a] = f;
+                    u[a] = xs[a] - (float)f;
+                }
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+                    const int ii = wrapc(i + cl[0] + dx, g.nx, g.px), jj = wrapc(j + cl[1] + dy, g.ny, g.py);
+                    const int kk = wrapc(k + cl[2] + dz, g.nz, g.pz);
+                    const float2 v = g.psi[(uint64_t)ii + (uint64_t)g.nx * ((uint64_t)jj + (uint64_t)g.ny * kk)];
+                    const float wgt = (dx ? u[0] : 1.f - u[0]) * (dy ? u[1] : 1.f - u[1]) * (dz ? u[2] : 1.f - u[2]);
+                    re += wgt * v.x;
+                    im += wgt * v.y;
+                }
+                o.cell = cell;
+                o.off[0] = x;
+                o.off[1] = y;
+                o.off[2] = z;
+                o.rho = re * re + im * im;
+                o.iters = 0;
+                o.status = (uint16_t)(VX_SAMPLE_SURROGATE | (np >= 4 ? VX_SAMPLE_MULTI : 0));
+                out[s] = o;
+            }
+        }
+        // queue the rest: one atomic per wavefront
+        const uint64_t qm = __ballot(queue);
+        if (qm) {
+            unsigned long long base = 0;
+            if (t == __builtin_ctzll(qm)) base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
+            base = __shfl(base, __builtin_ctzll(qm));
+            if (queue) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+                const int64_t k = (int64_t)base + rank;
+                fb_cell[k] = cell;
+                fb_desc[k] = (uint16_t)d;
+                fb_index[k] = s;
+            }
+        }
+    }
+}
+
+__global__ void zero_i64_k(int64_t *p) { *p = 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- host side
+
+struct vx_mlp {
+    vx_handle *h = nullptr;
+    int64_t max_batch = 0;
+    int64_t step = 0;
+    float *master = nullptr, *mom1 = nullptr, *mom2 = nullptr, *grad = nullptr;
+    __bf16 *w1t = nullptr, *w2t = nullptr, *w2c = nullptr, *w3t = nullptr;
+    float2 *gelu = nullptr, *dgelu = nullptr;
+    // training scratch
+    __bf16 *H1 = nullptr, *G1 = nullptr, *H2 = nullptr, *G2 = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
+    float *dZ3 = nullptr, *loss = nullptr;
+    // inference fallback queue (grown on demand)
+    int64_t fb_cap = 0;
+    uint64_t *fb_cell = nullptr;
+    uint16_t *fb_desc = nullptr;
+    int64_t *fb_index = nullptr;
+    int64_t *fb_count = nullptr;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+Net net_of(const vx_mlp *m) {
+    Net N;
+    N.master = m->master;
+    N.w1t = m->w1t;
+    N.w2t = m->w2t;
+    N.w2c = m->w2c;
+    N.w3t = m->w3t;
+    N.gelu = m->gelu;
+    N.dgelu = m->dgelu;
+    return N;
+}
+
+vx_status dalloc(vx_mlp *m, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return vx_hip_check(m->h, e, "vx_mlp: hipMalloc");
+    m->allocs.push_back(*p);
+    return VX_OK;
+}
+
+Geo geo_of(const vx_dims &d, const void *psi) {
+    Geo g;
+    g.psi = (const float2 *)psi;
+    g.nx = d.nx;
+    g.ny = d.ny;
+    g.nz = d.nz;
+    g.px = (int)(d.periodic & 1u);
+    g.py = (int)((d.periodic >> 1) & 1u);
+    g.pz = (int)((d.periodic >> 2) & 1u);
+    return g;
+}
+
+vx_status refresh(vx_mlp *m, hipStream_t s) {
+    hipLaunchKernelGGL(refresh_k, dim3(256), dim3(256), 0, s, m->master, m->w1t, m->w2t, m->w2c, m->w3t);
+    return vx_hip_check(m->h, hipGetLastError(), "vx_mlp: refresh");
+}
+
+// forward (training) + backward into m->grad
+vx_status grad_pass(vx_mlp *m, const uint16_t *feat, const float *target, const int32_t *idx, int64_t n, float lam,
+                    float tol, hipStream_t s) {
+    const Net N = net_of(m);
+    const unsigned tiles = (unsigned)((n + TM - 1) / TM);
+    const __bf16 *X = (const __bf16 *)feat;
+    hipLaunchKernelGGL(zero_f_k, dim3(1), dim3(64), 0, s, m->loss, 2);
+    hipLaunchKernelGGL(fwd_train_k, dim3(tiles), dim3(NT), 0, s, N, X, target, idx, n, lam, tol, m->H1, m->G1, m->H2,
+                       m->G2, m->dZ3, m->loss);
+    hipLaunchKernelGGL(bwd_rows_k, dim3(tiles), dim3(NT), 0, s, N, n, m->dZ3, m->H2, m->G1, m->G2, m->dZ2, m->dZ1,
+                       m->grad);
+    const unsigned chunks = (unsigned)((n + WCH - 1) / WCH);
+    hipLaunchKernelGGL(wgrad_k, dim3(chunks, NH / 128, NH / 128), dim3(NT), 0, s, (const __bf16 *)m->H1, NH,
+                       (const int32_t *)nullptr, (const __bf16 *)m->dZ2, NH, n, m->grad + OFF_W2);
+    hipLaunchKernelGGL(wgrad_k, dim3(chunks, NIN / 128, NH / 128), dim3(NT), 0, s, X, NIN, idx,
+                       (const __bf16 *)m->dZ1, NH, n, m->grad + OFF_W1);
+    return vx_hip_check(m->h, hipGetLastError(), "vx_mlp: gradient kernels");
+}
+
+vx_status check_n(vx_mlp *m, int64_t n) {
+    if (n < 1 || n > m->max_batch)
+        return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp: batch of %lld rows (1..%lld)", (long long)n,
+                       (long long)m->max_batch);
+    return VX_OK;
+}
+
+}  // namespace
+
+extern "C" vx_status vx_mlp_create(vx_handle *h, const float *h_params, int64_t max_batch, vx_mlp **out) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (!out || !h_params) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_create: null argument");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (1LL << 26)) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_create: max_batch");
+    if (vx_status st = vx_bind(h)) return st;
+    vx_mlp *m = new (std::nothrow) vx_mlp();
+    if (!m) return VX_ERR_NOMEM;
+    m->h = h;
+    m->max_batch = max_batch;
+    const size_t P4 = (size_t)NPARAM * 4;
+    const size_t act = (size_t)max_batch * NH * 2;
+    vx_status st = VX_OK;
+    void **fl[] = {(void **)&m->master, (void **)&m->mom1, (void **)&m->mom2, (void **)&m->grad};
+    for (void **p : fl)
+        if (st == VX_OK) st = dalloc(m, p, P4);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->w1t, (size_t)NIN * NH * 2);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->w2t, (size_t)NH * NH * 2);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->w2c, (size_t)NH * NH * 2);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->w3t, (size_t)16 * NH * 2);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->gelu, GT * sizeof(float2));
+    if (st == VX_OK) st = dalloc(m, (void **)&m->dgelu, GT * sizeof(float2));
+    void **ac[] = {(void **)&m->H1, (void **)&m->G1, (void **)&m->H2, (void **)&m->G2, (void **)&m->dZ2, (void **)&m->dZ1};
+    for (void **p : ac)
+        if (st == VX_OK) st = dalloc(m, p, act);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->dZ3, (size_t)max_batch * NOUT * 4);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->loss, 64);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->fb_count, 64);
+    if (st == VX_OK) st = vx_hip_check(h, hipMemcpy(m->master, h_params, P4, hipMemcpyHostToDevice), "vx_mlp_create");
+    if (st == VX_OK) st = vx_hip_check(h, hipMemset(m->mom1, 0, P4), "hipMemset");
+    if (st == VX_OK) st = vx_hip_check(h, hipMemset(m->mom2, 0, P4), "hipMemset");
+    if (st == VX_OK) st = vx_hip_check(h, hipMemset(m->grad, 0, P4), "hipMemset");
+    if (st == VX_OK) st = vx_hip_check(h, hipMemset(m->w3t, 0, (size_t)16 * NH * 2), "hipMemset");
+    if (st == VX_OK) {
+        hipLaunchKernelGGL(tables_k, dim3((GT + 255) / 256), dim3(256), 0, 0, m->gelu, m->dgelu);
+        st = refresh(m, 0);
+    }
+    if (st == VX_OK) st = vx_hip_check(h, hipDeviceSynchronize(), "vx_mlp_create");
+    if (st) {
+        vx_mlp_destroy(m);
+        return st;
+    }
+    *out = m;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_mlp_destroy(vx_mlp *m) {
+    if (!m) return VX_OK;
+    (void)vx_bind(m->h);
+    for (void *p : m->allocs) (void)hipFree(p);
+    delete m;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_mlp_get_params(vx_mlp *m, float *h_params) {
+    if (!m || !h_params) return VX_ERR_INVALID;
+    if (vx_status st = vx_bind(m->h)) return st;
+    return vx_hip_check(m->h, hipMemcpy(h_params, m->master, (size_t)NPARAM * 4, hipMemcpyDeviceToHost),
+                        "vx_mlp_get_params");
+}
+
+extern "C" vx_status vx_mlp_set_params(vx_mlp *m, const float *h_params) {
+    if (!m || !h_params) return VX_ERR_INVALID;
+    if (vx_status st = vx_bind(m->h)) return st;
+    vx_status st = vx_hip_check(m->h, hipMemcpy(m->master, h_params, (size_t)NPARAM * 4, hipMemcpyHostToDevice),
+                                "vx_mlp_set_params");
+    if (st == VX_OK) st = refresh(m, 0);
+    if (st == VX_OK) st = vx_hip_check(m->h, hipDeviceSynchronize(), "vx_mlp_set_params");
+    return st;
+}
+
+extern "C" vx_status vx_mlp_save(vx_mlp *m, const char *path) {
+    if (!m || !path) return VX_ERR_INVALID;
+    std::vector<float> p(NPARAM);
+    if (vx_status st = vx_mlp_get_params(m, p.data())) return st;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_save: cannot open %s", path);
+    const char magic[8] = {'V', 'X', 'M', 'L', 'P', '1', 0, 0};
+    const int64_t cnt = NPARAM;
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&cnt, 8, 1, f) == 1 &&
+              std::fwrite(p.data(), 4, NPARAM, f) == (size_t)NPARAM;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? VX_OK : vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_save: write failed");
+}
+
+extern "C" vx_status vx_mlp_load(vx_mlp *m, const char *path) {
+    if (!m || !path) return VX_ERR_INVALID;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_load: cannot open %s", path);
+    char magic[8];
+    int64_t cnt = 0;
+    std::vector<float> p(NPARAM);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "VXMLP1", 6) == 0 && std::fread(&cnt, 8, 1, f) == 1 &&
+              cnt == NPARAM && std::fread(p.data(), 4, NPARAM, f) == (size_t)NPARAM;
+    std::fclose(f);
+    if (!ok) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_load: %s is not a parameter file of this network", path);
+    return vx_mlp_set_params(m, p.data());
+}
+
+extern "C" vx_status vx_mlp_dataset(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                                    const uint16_t *d_cell_desc, const vx_sample *d_samples, const int64_t *d_count,
+                                    int64_t cap, uint16_t *d_feat, float *d_target, int64_t *d_n, int64_t n_cap,
+                                    vx_stream s) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (!d_psi || !d_cells || !d_cell_desc || !d_samples || !d_count || !d_feat || !d_target || !d_n)
+        return vx_fail(h, VX_ERR_INVALID, "vx_mlp_dataset: null pointer argument");
+    if (((uintptr_t)d_feat & 15u) != 0) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_dataset: d_feat must be 16-byte aligned");
+    if (cap < 0 || n_cap < 0) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_dataset: negative capacity");
+    if (cap == 0) return VX_OK;
+    if (vx_status st = vx_bind(h)) return st;
+    const unsigned blocks = (unsigned)((cap + TM - 1) / TM);
+    hipLaunchKernelGGL(dataset_k, dim3(blocks), dim3(NT), 0, (hipStream_t)s, geo_of(dims, d_psi), d_cells, d_cell_desc,
+                       d_samples, d_count, cap, (__bf16 *)d_feat, d_target, (unsigned long long *)d_n, n_cap);
+    return vx_hip_check(h, hipGetLastError(), "dataset_k launch");
+}
+
+extern "C" vx_status vx_mlp_features(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                                     const int64_t *d_count, int64_t cap, uint16_t *d_feat, vx_stream s) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (!d_psi || !d_cells || !d_count || !d_feat) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_features: null pointer");
+    if (cap < 0) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_features: negative capacity");
+    if (cap == 0) return VX_OK;
+    if (vx_status st = vx_bind(h)) return st;
+    hipLaunchKernelGGL(features_k, dim3((unsigned)((cap + TM - 1) / TM)), dim3(NT), 0, (hipStream_t)s,
+                       geo_of(dims, d_psi), d_cells, d_count, cap, (__bf16 *)d_feat);
+    return vx_hip_check(h, hipGetLastError(), "features_k launch");
+}
+
+extern "C" vx_status vx_mlp_train_step(vx_mlp *m, const uint16_t *d_feat, const float *d_target, const int32_t *d_idx,
+                                       int64_t n, const vx_adam_params *p, float *d_loss, vx_stream s) {
+    if (!m) return VX_ERR_INVALID;
+    m->h->err.clear();
+    if (!d_feat || !d_target || !p) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_train_step: null argument");
+    if (vx_status st = check_n(m, n)) return st;
+    if (!(p->lr > 0.f) || !(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f) || !(p->eps > 0.f))
+        return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_train_step: bad Adam parameters");
+    if (vx_status st = vx_bind(m->h)) return st;
+    hipStream_t hs = (hipStream_t)s;
+    vx_timer tm(m->h, hs, VX_KIND_MLP);
+    vx_status st = grad_pass(m, d_feat, d_target, d_idx, n, p->conf_lambda, p->conf_tol, hs);
+    if (st == VX_OK) {
+        ++m->step;
+        const float c1 = (float)(1.0 / (1.0 - std::pow((double)p->beta1, (double)m->step)));
+        const float c2 = (float)(1.0 / (1.0 - std::pow((double)p->beta2, (double)m->step)));
+        hipLaunchKernelGGL(adam_k, dim3(128), dim3(256), 0, hs, m->master, m->mom1, m->mom2, m->grad, p->lr, p->beta1,
+                           p->beta2, p->eps, c1, c2);
+        st = refresh(m, hs);
+        if (st == VX_OK && d_loss)
+            st = vx_hip_check(m->h, hipMemcpyAsync(d_loss, m->loss, 8, hipMemcpyDeviceToDevice, hs), "loss copy");
+    }
+    tm.stop();
+    return st;
+}
+
+extern "C" vx_status vx_mlp_grad(vx_mlp *m, const uint16_t *d_feat, const float *d_target, int64_t n, float conf_lambda,
+                                 float conf_tol, float *d_grad, float *d_loss, vx_stream s) {
+    if (!m) return VX_ERR_INVALID;
+    m->h->err.clear();
+    if (!d_feat || !d_target || !d_grad) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_grad: null argument");
+    if (vx_status st = check_n(m, n)) return st;
+    if (vx_status st = vx_bind(m->h)) return st;
+    hipStream_t hs = (hipStream_t)s;
+    vx_status st = grad_pass(m, d_feat, d_target, nullptr, n, conf_lambda, conf_tol, hs);
+    if (st == VX_OK) {
+        hipLaunchKernelGGL(copy_zero_k, dim3(128), dim3(256), 0, hs, m->grad, d_grad);
+        st = vx_hip_check(m->h, hipGetLastError(), "copy_zero_k");
+    }
+    if (st == VX_OK && d_loss)
+        st = vx_hip_check(m->h, hipMemcpyAsync(d_loss, m->loss, 8, hipMemcpyDeviceToDevice, hs), "loss copy");
+    return st;
+}
+
+extern "C" vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n, float *d_out, vx_stream s) {
+    if (!m) return VX_ERR_INVALID;
+    m->h->err.clear();
+    if (!d_feat || !d_out) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_forward: null argument");
+    if (n < 0) return vx_fail(m->h, VX_ERR_INVALID, "vx_mlp_forward: negative n");
+    if (n == 0) return VX_OK;
+    if (vx_status st = vx_bind(m->h)) return st;
+    hipLaunchKernelGGL(fwd_k, dim3((unsigned)((n + TM - 1) / TM)), dim3(NT), 0, (hipStream_t)s, net_of(m),
+                       (const __bf16 *)d_feat, n, d_out);
+    return vx_hip_check(m->h, hipGetLastError(), "fwd_k launch");
+}
+
+extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                                  const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
+                                  const vx_refine_params *p, vx_sample *d_out, vx_stream s) {
+    if (!m) return VX_ERR_INVALID;
+    vx_handle *h = m->h;
+    h->err.clear();
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (cap < 0) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_infer: negative capacity");
+    if (cap == 0) return VX_OK;
+    if (!d_psi || !d_cells || !d_cell_desc || !d_count || !d_out)
+        return vx_fail(h, VX_ERR_INVALID, "vx_mlp_infer: null pointer argument");
+    const vx_refine_params prm = p ? *p : vx_refine_defaults();
+    if (vx_status st = vx_check_refine_params(h, prm)) return st;
+    if (vx_status st = vx_bind(h)) return st;
+    if (cap > m->fb_cap) {  // fallback queue sized for the whole list
+        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index}) {
+            if (!q) continue;
+            (void)hipFree(q);
+            for (auto &a : m->allocs)
+                if (a == q) a = nullptr;
+        }
+        m->fb_cell = nullptr;
+        m->fb_desc = nullptr;
+        m->fb_index = nullptr;
+        m->fb_cap = 0;
+        vx_status st = dalloc(m, (void **)&m->fb_cell, (size_t)cap * 8);
+        if (st == VX_OK) st = dalloc(m, (void **)&m->fb_desc, (size_t)cap * 2);
+        if (st == VX_OK) st = dalloc(m, (void **)&m->fb_index, (size_t)cap * 8);
+        if (st) return st;
+        m->fb_cap = cap;
+    }
+    hipStream_t hs = (hipStream_t)s;
+    vx_timer tm(h, hs, VX_KIND_MLP);
+    hipLaunchKernelGGL(zero_i64_k, dim3(1), dim3(1), 0, hs, m->fb_count);
+    hipLaunchKernelGGL(infer_k, dim3((unsigned)((cap + TM - 1) / TM)), dim3(NT), 0, hs, net_of(m), geo_of(dims, d_psi),
+                       d_cells, d_cell_desc, d_count, cap, conf_threshold, d_out, m->fb_cell, m->fb_desc, m->fb_index,
+                       m->fb_count);
+    tm.stop();
+    vx_status st = vx_hip_check(h, hipGetLastError(), "infer_k launch");
+    if (st) return st;
+    return vx_refine_launch(h, dims, d_psi, m->fb_cell, m->fb_desc, nullptr, m->fb_count, cap, prm, d_out, hs,
+                            m->fb_index);
+}

@@ -30,6 +30,7 @@ struct RefArgs {
     const int64_t *count;
     int64_t cap;
     vx_sample *out;
+    const int64_t *out_index;    // nullable: sample s is written to out[out_index[s]]
     unsigned long long *chunks;  // chunk counter, zero at launch
     int nx, ny, nz;
     int px, py, pz;
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                         o.cell = cell;
                         o.rho = -1.f;
                         o.status = (uint16_t)VX_SAMPLE_BAD_CELL;
-                        out_p[s] = o;
+                        out_p[(!BATCH && A.out_index) ? A.out_index[s] : s] = o;
                     } else {
                         uint64_t rxy, ri;
                         gk = (int)divmod53(cell, nxy, rnxy, rxy);
@@ -523,7 +524,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             o.status = (uint16_t)status;
             o.reserved = 0;
             if constexpr (BATCH) s_fr[fr].out[s] = o;
-            else A.out[s] = o;
+            else A.out[A.out_index ? A.out_index[s] : s] = o;
             phase = PH_IDLE;
         }
     }
@@ -552,8 +553,9 @@ int64_t ref_blocks(vx_handle *h, K kernel, int &per_cu, int64_t cap) {
 
 vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
                            const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
-                           const vx_refine_params &p, vx_sample *out, hipStream_t s) {
+                           const vx_refine_params &p, vx_sample *out, hipStream_t s, const int64_t *out_index) {
     RefArgs A;
+    A.out_index = out_index;
     A.psi = (const float2 *)psi;
     A.cells = cells;
     A.desc = desc;

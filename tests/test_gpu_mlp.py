@@ -1,0 +1,240 @@
+"""Surrogate network kernels against the FP64 oracle network (oracle.mlp).
+
+The GPU computes with BF16 matrix operands and FP32 accumulation, and reads gelu from tables; the
+oracle computes in FP64 from the same BF16-rounded inputs and weights. Gradients must agree to
+2e-2 in relative L2 norm per parameter tensor, forward outputs to the BF16 rounding of the hidden
+activations. Inference with an unreachable threshold must reproduce the plain refinement sample by
+sample; with threshold 0 every eligible cell must carry exactly x0 + the network's output.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import vxinputs
+from oracle import mlp as M
+
+from gpu_util import log, run_winding, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ex():
+    from paper_1911_12070_amd import Extractor
+    e = Extractor(0)
+    yield e
+    e.close()
+
+
+def bf16_params(P):
+    """Weights as the GPU sees them: BF16-rounded matrices, FP32 biases."""
+    Q = {}
+    for k, v in P.items():
+        Q[k] = M.bf16(v) if k.startswith("W") else np.asarray(v, np.float32).astype(np.float64)
+    return Q
+
+
+def upload_bf16(x):
+    import torch
+    return torch.from_numpy(np.asarray(x, np.float32)).to(torch.bfloat16).contiguous().cuda()
+
+
+def make_mlp(ex, P, max_batch=4096):
+    from paper_1911_12070_amd import vx_mlp_create
+    return vx_mlp_create(ex.h, vxinputs.mlp_pack(P), max_batch)
+
+
+@pytest.mark.parametrize("n", [300, 1000])
+def test_gradients_match_oracle(ex, n):
+    import torch
+    from paper_1911_12070_amd import MLP_NPARAMS, vx_mlp_destroy, vx_mlp_grad
+    rng = np.random.default_rng(n)
+    P = vxinputs.mlp_init(11)
+    for k in ("b1", "b2", "b3"):
+        P[k] = rng.normal(0, 0.2, P[k].shape)
+    P["W3"] = P["W3"] * 10.0
+    X = M.bf16(rng.normal(size=(n, 128)))
+    Q = bf16_params(P)
+    Z3 = M.forward(Q, X)["Z3"]
+    # targets clearly inside or clearly outside the confidence tolerance
+    T = Z3[:, :3] + np.where(rng.random((n, 1)) < 0.5, 0.002, 0.3) * np.sign(rng.normal(size=(n, 3)))
+    lam, tol = 0.3, 0.02
+    loss, G, y = M.loss_grad(Q, X, T, lam=lam, tol=tol)
+    m = make_mlp(ex, P)
+    grad = torch.zeros(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    lossd = torch.zeros(2, dtype=torch.float32, device="cuda")
+    vx_mlp_grad(ex.h, m, upload_bf16(X), torch.from_numpy(T.astype(np.float32)).cuda(), n, lam, tol, grad, lossd)
+    torch.cuda.synchronize()
+    Gg = vxinputs.mlp_unpack(grad.cpu().numpy())
+    for k in M.NAMES:
+        rel = np.linalg.norm(Gg[k] - G[k]) / np.linalg.norm(G[k])
+        log(f"n={n} grad {k}: rel L2 {rel:.2e}")
+        assert rel <= 2e-2, (k, rel)
+    mse = float(np.mean(((Z3[:, :3] - T) ** 2).sum(1)))
+    lg = lossd.cpu().numpy()
+    assert lg[0] == pytest.approx(mse, rel=2e-2)
+    assert lg[0] + lam * lg[1] == pytest.approx(loss, rel=2e-2)
+    vx_mlp_destroy(ex.h, m)
+
+
+def test_forward_matches_oracle(ex):
+    import torch
+    from paper_1911_12070_amd import vx_mlp_destroy, vx_mlp_forward
+    rng = np.random.default_rng(2)
+    n = 777
+    P = vxinputs.mlp_init(12)
+    P["W3"] = P["W3"] * 10.0
+    X = M.bf16(rng.normal(size=(n, 128)))
+    Q = bf16_params(P)
+    Z3 = M.forward(Q, X)["Z3"]
+    m = make_mlp(ex, P)
+    out = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    vx_mlp_forward(ex.h, m, upload_bf16(X), n, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().astype(np.float64)
+    scale = np.abs(Z3[:, :3]).max()
+    err = np.abs(o[:, :3] - Z3[:, :3]).max() / scale
+    conf_err = np.abs(o[:, 3] - M.sigmoid(Z3[:, 3])).max()
+    log(f"forward: max rel err {err:.2e}, conf err {conf_err:.2e}")
+    assert err < 2e-2 and conf_err < 1e-2
+    vx_mlp_destroy(ex.h, m)
+
+
+def test_adam_step_matches_oracle(ex):
+    import torch
+    from paper_1911_12070_amd import AdamParams, vx_mlp_destroy, vx_mlp_get_params, vx_mlp_train_step
+    rng = np.random.default_rng(4)
+    n = 512
+    P = vxinputs.mlp_init(13)
+    P["W3"] = P["W3"] * 10.0
+    P = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in P.items()}  # FP32 master weights
+    X = M.bf16(rng.normal(size=(n, 128)))
+    Z3 = M.forward(bf16_params(P), X)["Z3"]
+    T = Z3[:, :3] + 0.3
+    lr = 1e-3
+    _, G, _ = M.loss_grad(bf16_params(P), X, T, lam=0.1, tol=0.02)
+    zeros = {k: np.zeros_like(v) for k, v in P.items()}
+    P1, _, _ = M.adam(P, G, zeros, zeros, 1, lr)
+    m = make_mlp(ex, P)
+    vx_mlp_train_step(ex.h, m, upload_bf16(X), torch.from_numpy(T.astype(np.float32)).cuda(), None, n,
+                      AdamParams(lr, 0.9, 0.999, 1e-8, 0.1, 0.02))
+    torch.cuda.synchronize()
+    P1g = vxinputs.mlp_unpack(vx_mlp_get_params(ex.h, m))
+    for k in M.NAMES:
+        dg, do = P1g[k] - P[k], P1[k] - P[k]
+        big = np.abs(G[k]) > 1e-2 * np.abs(G[k]).max()  # the first step is lr * sign(g) where g is clearly nonzero
+        agree = np.mean(np.abs(dg[big] - do[big]) < 0.05 * lr)
+        log(f"adam {k}: {agree:.4f} of {big.sum()} clear updates agree")
+        assert agree > 0.99, k
+        assert np.abs(dg).max() <= lr * 1.001
+    vx_mlp_destroy(ex.h, m)
+
+
+def field_cells(ex, seed=21, shape=(48, 40, 36), periodic=7):
+    t = vxinputs.make_tangle((64, 64, 64), 256, (3, 7), seed)
+    psi_np = vxinputs.eval_tangle(t, (0, 0, 0, *shape))
+    psi = to_dev(psi_np)
+    out = run_winding(ex, psi, periodic)
+    return psi_np, psi, out
+
+
+def test_features_match_oracle(ex):
+    import torch
+    from paper_1911_12070_amd import dims, vx_mlp_features
+    psi_np, psi, out = field_cells(ex)
+    nc = int(out["counts"][1])
+    feat = torch.zeros((nc, 128), dtype=torch.bfloat16, device="cuda")
+    nz, ny, nx = psi_np.shape
+    vx_mlp_features(ex.h, dims(nx, ny, nz, 7), psi, out["cells"], out["counts"][1:], nc, feat)
+    torch.cuda.synchronize()
+    g = feat.float().cpu().numpy().astype(np.float64)
+    cells = out["cells"][:nc].cpu().numpy()
+    worst = 0.0
+    for r in range(0, nc, max(1, nc // 400)):
+        re, im = oracle.gather_patch(psi_np, int(cells[r]))
+        f = M.features(re, im)
+        # BF16 of an FP32-normalised value vs the FP64 value: within one BF16 step (2^-8 relative)
+        worst = max(worst, float(np.max(np.abs(g[r] - f) / np.maximum(np.abs(f), 1e-3))))
+    log(f"features: worst relative deviation {worst:.2e}")
+    assert worst <= 2.0 ** -8 + 1e-6
+
+
+def test_dataset_rows(ex):
+    import torch
+    from paper_1911_12070_amd import dims, samples_to_numpy, vx_mlp_dataset
+    psi_np, psi, out = field_cells(ex, seed=22, shape=(64, 64, 48))
+    smp = ex.refine(psi, out, 7)
+    torch.cuda.synchronize()
+    nc = int(out["counts"][1])
+    feat = torch.zeros((nc, 128), dtype=torch.bfloat16, device="cuda")
+    target = torch.zeros((nc, 3), dtype=torch.float32, device="cuda")
+    n_out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nz, ny, nx = psi_np.shape
+    vx_mlp_dataset(ex.h, dims(nx, ny, nz, 7), psi, out["cells"], out["cdesc"], smp, out["counts"][1:], nc, feat,
+                   target, n_out, nc)
+    torch.cuda.synchronize()
+    k = int(n_out.cpu())
+    s = samples_to_numpy(smp, nc)
+    cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    bad = 1 | 4 | 8 | 16 | 32 | 64
+    expect = ((s["status"] & bad) == 0)
+    log(f"dataset: {k} rows of {nc} samples ({expect.sum()} eligible)")
+    assert k == int(expect.sum())
+    # every row is the features and target of one eligible sample
+    F = feat[:k].float().cpu().numpy()
+    Tg = target[:k].cpu().numpy()
+    byfeat = {}
+    for i in np.nonzero(expect)[0]:
+        re, im = oracle.gather_patch(psi_np, int(s["cell"][i]))
+        byfeat[M.bf16(M.features(re, im)).astype(np.float32).tobytes()] = i
+    hits = 0
+    for r in range(k):
+        i = byfeat.get(F[r].tobytes())
+        if i is None:
+            continue
+        hits += 1
+        assert np.allclose(Tg[r], s["off"][i] - M.first_estimate(int(cdesc[i])), atol=1e-6)
+    assert hits >= 0.95 * k
+
+
+def test_infer_fallback_and_surrogate(ex, tmp_path):
+    import torch
+    from paper_1911_12070_amd import (SAMPLE_SURROGATE, dims, samples_to_numpy, vx_mlp_destroy, vx_mlp_features,
+                                      vx_mlp_forward, vx_mlp_get_params, vx_mlp_infer, vx_mlp_load, vx_mlp_save)
+    psi_np, psi, out = field_cells(ex, seed=23, shape=(64, 48, 40))
+    nc = int(out["counts"][1])
+    nz, ny, nx = psi_np.shape
+    d = dims(nx, ny, nz, 7)
+    plain = samples_to_numpy(ex.refine(psi, out, 7), nc)
+    m = make_mlp(ex, vxinputs.mlp_init(14))
+    res = torch.zeros((nc, 8), dtype=torch.int32, device="cuda")
+    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], nc, 2.0, res)
+    torch.cuda.synchronize()
+    a = samples_to_numpy(res, nc)
+    assert a.tobytes() == plain.tobytes(), "threshold above 1 must reproduce the plain refinement"
+    res.fill_(0)
+    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], nc, 0.0, res)
+    feat = torch.zeros((nc, 128), dtype=torch.bfloat16, device="cuda")
+    vx_mlp_features(ex.h, d, psi, out["cells"], out["counts"][1:], nc, feat)
+    fo = torch.zeros((nc, 4), dtype=torch.float32, device="cuda")
+    vx_mlp_forward(ex.h, m, feat, nc, fo)
+    torch.cuda.synchronize()
+    b = samples_to_numpy(res, nc)
+    fo = fo.cpu().numpy()
+    cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    sur = (b["status"] & SAMPLE_SURROGATE) != 0
+    npierced = np.array([bin(int(v) & 0x555 | (int(v) >> 1) & 0x555).count("1") for v in cdesc])
+    log(f"threshold 0: {sur.sum()} of {nc} cells from the surrogate")
+    assert np.array_equal(sur, npierced == 2)
+    for i in np.nonzero(sur)[0][:500]:
+        x0 = M.first_estimate(int(cdesc[i])).astype(np.float32)
+        assert np.array_equal(b["off"][i], (x0 + fo[i, :3]).astype(np.float32))
+        assert b["iters"][i] == 0
+    assert b[~sur].tobytes() == plain[~sur].tobytes()
+    path = str(tmp_path / "w.bin")
+    vx_mlp_save(ex.h, m, path)
+    m2 = make_mlp(ex, vxinputs.mlp_init(99))
+    vx_mlp_load(ex.h, m2, path)
+    assert np.array_equal(vx_mlp_get_params(ex.h, m2), vx_mlp_get_params(ex.h, m))
+    vx_mlp_destroy(ex.h, m)
+    vx_mlp_destroy(ex.h, m2)
