@@ -98,6 +98,27 @@ def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0, label: str | 
     }
 
 
+def bench_surrogate(ex):
+    """Surrogate path (committed trained network, fallback below confidence 0.9) against the plain
+    refinement on every pierced cell of the fresh-seed 512^3 tangle (2048 waves, |n| in [6,16],
+    seed 5); kernel times from HIP events, position errors against the plain result."""
+    import numpy as np
+
+    import vxinputs
+    from paper_1911_12070_amd import vx_mlp_create, vx_mlp_destroy, vx_mlp_load
+    from paper_1911_12070_amd.surrogate import evaluate
+    path = os.path.join(ROOT, "paper_1911_12070_amd", "weights", "surrogate_c2.bin")
+    if not os.path.exists(path):
+        return None
+    print("[bench] surrogate vs plain refinement on the 512^3 tangle", file=sys.stderr, flush=True)
+    m = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    vx_mlp_load(ex.h, m, path)
+    r = evaluate(ex, m, vxinputs.tangle_512(), 0.9)
+    vx_mlp_destroy(ex.h, m)
+    r["workload"] = "tangle_512: 512^3 periodic random-wave tangle, 2048 waves, |n| in [6,16], seed 5 (unseen)"
+    return r
+
+
 def calib_copy():
     """Kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
     (fill: writes 1 GiB; sum: reads 1 GiB)."""
@@ -328,6 +349,9 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    del psi, out, samples
+    torch.cuda.empty_cache()
+    res["surrogate"] = bench_surrogate(ex)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(tangle)

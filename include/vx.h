@@ -212,7 +212,7 @@ vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_
 #define VX_MLP_NHID 256
 #define VX_MLP_NOUT 4
 #define VX_MLP_NPARAMS 99844
-#define VX_SAMPLE_SURROGATE 128u  /* position from the surrogate network (iters = 0) */
+#define VX_SAMPLE_SURROGATE 128u  /* position from the surrogate network + one Newton step */
 
 typedef struct vx_mlp vx_mlp;
 typedef struct {
@@ -258,11 +258,14 @@ vx_status vx_mlp_grad(vx_mlp *m, const uint16_t *d_feat, const float *d_target, 
 /* Network outputs for rows 0..n-1: d_out[n][4] = (Z3[0], Z3[1], Z3[2], conf). */
 vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n, float *d_out, vx_stream s);
 
-/* Core samples of the listed cells (as vx_refine) through the surrogate: a cell gets the
- * network's position x0 + Z3[0..2] (status VX_SAMPLE_SURROGATE, rho = |trilinear psi|^2 there,
- * iters 0) when conf >= conf_threshold, its first estimate has two pierced faces and its patch lies
- * inside the grid; every other cell is refined by the plain method with p (NULL = defaults),
- * exactly as vx_refine would. No host synchronisation. */
+/* Core samples of the listed cells (as vx_refine) through the surrogate. A cell whose first
+ * estimate has two pierced faces, whose patch lies inside the grid and whose conf >= conf_threshold
+ * gets the network's point x0 + Z3[0..2], projected onto the refinement's plane (through x0, normal
+ * to grad Re psi x grad Im psi at x0) and polished by one Newton step on (Re psi, Im psi) in that
+ * plane, FP32 (status VX_SAMPLE_SURROGATE, iters 1, rho = |trilinear psi|^2 there). Every other
+ * cell, and every cell whose polish fails (degenerate tangent, singular Jacobian, point outside
+ * the patch), is refined by the plain method with p (NULL = defaults), exactly as vx_refine would.
+ * No host synchronisation. */
 vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
                        const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
                        const vx_refine_params *p, vx_sample *d_out, vx_stream s);
@@ -322,7 +325,8 @@ vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char 
 
 /* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).
- * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate inference, 3 = batch.
+ * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate network (inference: the network
+ * kernel; training: a whole step), 3 = batch, 4 = surrogate polish.
  * ---------------------------------------------------------------------------------------- */
 vx_status vx_profile_enable(vx_handle *h, int enable); /* enabling clears the accumulators */
 /* Sum of the recorded kernel durations (ms) and their number; synchronises the recorded events. */

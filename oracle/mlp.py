@@ -122,3 +122,57 @@ def bf16(x: np.ndarray) -> np.ndarray:
     u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
     r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _plane(re, im, desc):
+    """First estimate x0 and the in-plane basis (e1, e2) of the refinement at x0 (Sec. 3.3.3): t is
+    grad Re psi x grad Im psi of the trilinear patch; e1 = t x u / |t x u| with u the axis of the
+    smallest |t_i|, e2 = t x e1. None when t is degenerate (the refinement then uses the face
+    flux; the surrogate leaves such cells to it)."""
+    from . import trilerp
+    x0 = first_estimate(desc)
+    _, g = trilerp(re, im, x0)
+    gr, gi = g.real, g.imag
+    t = np.cross(gr, gi)
+    tn = np.linalg.norm(t)
+    if not (tn > 1e-6 * np.linalg.norm(gr) * np.linalg.norm(gi)) or tn == 0.0:
+        return None
+    t = t / tn
+    u = np.zeros(3)
+    u[int(np.argmin(np.abs(t)))] = 1.0
+    e1 = np.cross(t, u)
+    e1 /= np.linalg.norm(e1)
+    return x0, e1, np.cross(t, e1)
+
+
+def inside(x) -> bool:
+    return bool(np.all(x >= -1.0) and np.all(x <= 2.0))
+
+
+def polish(re, im, desc: int, x_start):
+    """The surrogate's final step: x_start (the network's point) projected onto the refinement's
+    plane through x0, then one Newton step on (Re psi, Im psi) in that plane (the refinement's
+    polish, Sec. 3.3.3 reading). Returns (x, |psi(x)|^2), or None where the refinement must run
+    instead: degenerate tangent, singular Jacobian, or a point outside the patch."""
+    from . import trilerp
+    pl = _plane(re, im, desc)
+    if pl is None:
+        return None
+    x0, e1, e2 = pl
+    d = np.asarray(x_start, np.float64) - x0
+    y = np.array([d @ e1, d @ e2])
+    xp = x0 + y[0] * e1 + y[1] * e2
+    if not inside(xp):
+        return None
+    v, g = trilerp(re, im, xp)
+    J = np.array([[e1 @ g.real, e2 @ g.real], [e1 @ g.imag, e2 @ g.imag]])
+    det = J[0, 0] * J[1, 1] - J[0, 1] * J[1, 0]
+    if det == 0.0:
+        return None
+    dy = -np.array([J[1, 1] * v.real - J[0, 1] * v.imag, -J[1, 0] * v.real + J[0, 0] * v.imag]) / det
+    y = y + dy
+    x = x0 + y[0] * e1 + y[1] * e2
+    if not inside(x):
+        return None
+    v, _ = trilerp(re, im, x)
+    return x, float(abs(v) ** 2)

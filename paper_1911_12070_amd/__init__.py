@@ -25,7 +25,7 @@ SAMPLE_NOT_CONVERGED = 16
 SAMPLE_NO_FACES = 32
 SAMPLE_BAD_CELL = 64
 
-KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH = 0, 1, 2, 3
+KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH = 0, 1, 2, 3, 4
 
 # every symbol include/vx.h declares
 EXPORTS = ["vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",

@@ -150,6 +150,95 @@ __device__ __forceinline__ void first_estimate(uint32_t desc, float &x, float &y
     }
 }
 
+// trilinear psi and its gradient (cell units) at cell-local x, from the corners of the patch cell
+// that holds x (clamped to the 3x3x3 cells of the patch), FP32, read from the field
+__device__ __forceinline__ void tri_eval(const Geo &g, int i, int j, int k, const float x[3], float &vr, float &vi,
+                                         float gr[3], float gi[3]) {
+    int cl[3];
+    float u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int f = (int)floorf(x[a]);
+        f = max(-1, min(f, 1));
+        cl[a] = f;
+        u[a] = x[a] - (float)f;
+    }
+    float2 c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int ii = wrapc(i + cl[0] + (q & 1), g.nx, g.px), jj = wrapc(j + cl[1] + ((q >> 1) & 1), g.ny, g.py);
+        const int kk = wrapc(k + cl[2] + (q >> 2), g.nz, g.pz);
+        c[q] = g.psi[(uint64_t)ii + (uint64_t)g.nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk)];
+    }
+    const float ux = u[0], uy = u[1], uz = u[2], mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
+    const float2 a00 = make_float2(mx * c[0].x + ux * c[1].x, mx * c[0].y + ux * c[1].y);
+    const float2 a10 = make_float2(mx * c[2].x + ux * c[3].x, mx * c[2].y + ux * c[3].y);
+    const float2 a01 = make_float2(mx * c[4].x + ux * c[5].x, mx * c[4].y + ux * c[5].y);
+    const float2 a11 = make_float2(mx * c[6].x + ux * c[7].x, mx * c[6].y + ux * c[7].y);
+    const float2 b0 = make_float2(my * a00.x + uy * a10.x, my * a00.y + uy * a10.y);
+    const float2 b1 = make_float2(my * a01.x + uy * a11.x, my * a01.y + uy * a11.y);
+    vr = mz * b0.x + uz * b1.x;
+    vi = mz * b0.y + uz * b1.y;
+    gr[2] = b1.x - b0.x;
+    gi[2] = b1.y - b0.y;
+    gr[1] = mz * (a10.x - a00.x) + uz * (a11.x - a01.x);
+    gi[1] = mz * (a10.y - a00.y) + uz * (a11.y - a01.y);
+    const float dx0 = my * (c[1].x - c[0].x) + uy * (c[3].x - c[2].x), dx1 = my * (c[5].x - c[4].x) + uy * (c[7].x - c[6].x);
+    const float dy0 = my * (c[1].y - c[0].y) + uy * (c[3].y - c[2].y), dy1 = my * (c[5].y - c[4].y) + uy * (c[7].y - c[6].y);
+    gr[0] = mz * dx0 + uz * dx1;
+    gi[0] = mz * dy0 + uz * dy1;
+}
+
+__device__ __forceinline__ bool in_patch(const float x[3]) {
+    return x[0] >= -1.f && x[0] <= 2.f && x[1] >= -1.f && x[1] <= 2.f && x[2] >= -1.f && x[2] <= 2.f;
+}
+
+// The surrogate's final step (the refinement's Newton polish, Sec. 3.3.3 reading): the network's
+// point xs projected onto the plane through x0 normal to t = grad Re psi x grad Im psi at x0, then
+// one Newton step on (Re psi, Im psi) in that plane. False where the plain refinement must run:
+// degenerate t, singular Jacobian, or a point outside the patch.
+__device__ bool polish(const Geo &g, int i, int j, int k, const float x0[3], const float xs[3], float out[3],
+                       float &rho) {
+    float vr, vi, gr[3], gi[3];
+    tri_eval(g, i, j, k, x0, vr, vi, gr, gi);
+    float t[3] = {gr[1] * gi[2] - gr[2] * gi[1], gr[2] * gi[0] - gr[0] * gi[2], gr[0] * gi[1] - gr[1] * gi[0]};
+    const float tn = sqrtf(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    const float nr = sqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+    const float ni = sqrtf(gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2]);
+    if (!(tn > 1e-6f * nr * ni) || tn == 0.f) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t[a] /= tn;
+    int ax = 0;
+    if (fabsf(t[1]) < fabsf(t[ax])) ax = 1;
+    if (fabsf(t[2]) < fabsf(t[ax])) ax = 2;
+    const float uu[3] = {ax == 0 ? 1.f : 0.f, ax == 1 ? 1.f : 0.f, ax == 2 ? 1.f : 0.f};
+    float e1[3] = {t[1] * uu[2] - t[2] * uu[1], t[2] * uu[0] - t[0] * uu[2], t[0] * uu[1] - t[1] * uu[0]};
+    const float n1 = sqrtf(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) e1[a] /= n1;
+    const float e2[3] = {t[1] * e1[2] - t[2] * e1[1], t[2] * e1[0] - t[0] * e1[2], t[0] * e1[1] - t[1] * e1[0]};
+    const float d[3] = {xs[0] - x0[0], xs[1] - x0[1], xs[2] - x0[2]};
+    float y1 = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
+    float y2 = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
+    float xp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xp[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
+    if (!in_patch(xp)) return false;
+    tri_eval(g, i, j, k, xp, vr, vi, gr, gi);
+    const float j00 = e1[0] * gr[0] + e1[1] * gr[1] + e1[2] * gr[2], j01 = e2[0] * gr[0] + e2[1] * gr[1] + e2[2] * gr[2];
+    const float j10 = e1[0] * gi[0] + e1[1] * gi[1] + e1[2] * gi[2], j11 = e2[0] * gi[0] + e2[1] * gi[1] + e2[2] * gi[2];
+    const float det = j00 * j11 - j01 * j10;
+    if (det == 0.f) return false;
+    y1 += -(j11 * vr - j01 * vi) / det;
+    y2 += -(-j10 * vr + j00 * vi) / det;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
+    if (!in_patch(out)) return false;
+    tri_eval(g, i, j, k, out, vr, vi, gr, gi);
+    rho = vr * vr + vi * vi;
+    return true;
+}
+
 // ---------------------------------------------------------------------------- layer building blocks
 
 // acc = A (64 x K, LDS, pitch AP) times B (K x 64: columns n0 .. n0+63 of a K-contiguous weight
@@ -547,6 +636,7 @@ __global__ __launch_bounds__(NT) void fwd_k(Net N, const __bf16 *__restrict__ fe
 __global__ __launch_bounds__(NT) void features_k(Geo g, const uint64_t *__restrict__ cells,
                                                  const int64_t *__restrict__ count, int64_t cap, __bf16 *feat) {
     const int64_t n = min(*count, cap);
+    if ((int64_t)blockIdx.x * TM >= n) return;  // uniform per workgroup
     const int64_t s = (int64_t)blockIdx.x * TM + (threadIdx.x >> 2);
     const int c = threadIdx.x & 3;
     const bool ok = s < n;
@@ -563,6 +653,7 @@ __global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restric
                                                 int64_t cap, __bf16 *feat, float *target, unsigned long long *d_n,
                                                 int64_t n_cap) {
     const int64_t n = min(*count, cap);
+    if ((int64_t)blockIdx.x * TM >= n) return;  // uniform per workgroup
     const int64_t s = (int64_t)blockIdx.x * TM + (threadIdx.x >> 2);
     const int c = threadIdx.x & 3;
     const uint32_t bad = VX_SAMPLE_MULTI | VX_SAMPLE_NO_FACES | VX_SAMPLE_NONZERO_MIN | VX_SAMPLE_NOT_CONVERGED |
@@ -597,104 +688,220 @@ __global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restric
     }
 }
 
-// Inference: 64 listed cells per workgroup. Confident single-core interior cells get the network's
-// sample; the others are queued (cell, descriptor, position in the list) for the plain refinement.
-__global__ __launch_bounds__(NT) void infer_k(Net N, Geo g, const uint64_t *__restrict__ cells,
-                                              const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
-                                              int64_t cap, float thr, vx_sample *out, uint64_t *fb_cell,
-                                              uint16_t *fb_desc, int64_t *fb_index, int64_t *fb_count) {
+constexpr int NK1 = NIN / 32, NK2 = NH / 32;  // k-steps of the two hidden layers
+constexpr int NTI = 512;                        // inference workgroup: 8 wavefronts
+
+// Workgroup barrier for LDS traffic only: this wavefront's LDS operations are complete, global loads
+// may still be in flight (they land in registers that are not read before their own wait).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Inference, part 1: the network for every listed cell. Persistent: one workgroup of 8 wavefronts
+// per CU walks the 64-cell tiles; wavefront w owns columns 32w .. 32w+31 of both hidden layers and
+// loads their B operands once (24 16-byte fragments kept in registers for the whole run, plus the
+// head's 8 for the wavefronts that compute it), instead of once per tile; the gelu table is loaded
+// once per workgroup. Small per-wavefront register footprints leave room for two wavefronts per
+// SIMD. The patch nodes of the next tile are requested before the current tile's layers run, the
+// cell ids one tile further ahead; the workgroup synchronises with LDS-only barriers so that those
+// loads stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
+__global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
+                                                   const int64_t *__restrict__ count, int64_t cap, float4 *net_out) {
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
     __shared__ float2 sg[GT];
     __shared__ float sOut[TM * NOUT];
-    __shared__ int sUse[TM];
     const int64_t n = min(*count, cap);
-    const int64_t row0 = (int64_t)blockIdx.x * TM;
-    if (row0 >= n) return;  // uniform per workgroup
-    const int t = threadIdx.x;
-    load_tables(N, sg, nullptr);
-    {
-        const int r = t >> 2, c = t & 3;
-        const int64_t s = row0 + r;
-        uint64_t cell = s < n ? cells[s] : 0;
-        const uint64_t ncell = (uint64_t)g.nx * g.ny * g.nz;
-        int i = 0, j = 0, k = 0;
-        bool use = s < n && cell < ncell;
-        if (use) {
-            cell_xyz(cell, g, i, j, k);
-            use = interior(g, i, j, k);
-        }
-        gather_features(g, i, j, k, c, sX + r * XP);
-        if (c == 0) sUse[r] = use ? 1 : 0;
+    const int64_t ntiles = (n + TM - 1) / TM;
+    if ((int64_t)blockIdx.x >= ntiles) return;  // uniform per workgroup
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, n0 = 32 * w;
+    const int64_t G = gridDim.x;
+    for (int i = t; i < GT; i += NTI) sg[i] = N.gelu[i];
+    bf16x8 b1[2][NK1], b2[2][NK2], b3[NK2];
+    float bias1[2], bias2[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int col = n0 + 16 * c + (l & 15);
+        bias1[c] = N.master[OFF_B1 + col];
+        bias2[c] = N.master[OFF_B2 + col];
+#pragma unroll
+        for (int kk = 0; kk < NK1; ++kk) b1[c][kk] = ld8(N.w1t + col * NIN + 32 * kk + 8 * (l >> 4));
+#pragma unroll
+        for (int kk = 0; kk < NK2; ++kk) b2[c][kk] = ld8(N.w2t + col * NH + 32 * kk + 8 * (l >> 4));
     }
-    __syncthreads();
-    hidden(N, sX, sH, sg, nullptr, row0, n, nullptr, nullptr, nullptr, nullptr);
-    outputs(N, sH, sOut);
-    if (t < 64) {
-        const int64_t s = row0 + t;
-        bool mine = false, queue = false;
-        uint64_t cell = 0;
-        uint32_t d = 0;
-        vx_sample o{};
-        if (s < n) {
-            cell = cells[s];
-            d = desc[s];
-            float x0, y0, z0;
-            int np;
-            first_estimate(d, x0, y0, z0, np);
-            const float conf = 1.f / (1.f + expf(-sOut[t * NOUT + 3]));
-            mine = sUse[t] && np == 2 && conf >= thr;
-            queue = !mine;
-            if (mine) {
-                const float x = x0 + sOut[t * NOUT + 0], y = y0 + sOut[t * NOUT + 1], z = z0 + sOut[t * NOUT + 2];
-                // |psi|^2 of the trilinear interpolant at the sample (cell of the patch that holds it)
-                int i, j, k;
-                cell_xyz(cell, g, i, j, k);
-                const float xs[3] = {x, y, z};
-                int cl[3];
-                float u[3];
+    const bool headw = w < TM / 16;  // wavefronts 0..3 compute the head for rows 16w .. 16w+15
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    int f = (int)floorf(xs[a]);
-                    f = max(-1, min(f, 1));
-                    cl[a] = f;
-                    u[a] = xs[a] - (float)f;
-                }
-                float re = 0.f, im = 0.f;
+    for (int kk = 0; kk < NK2; ++kk) b3[kk] = ld8(N.w3t + (l & 15) * NH + 32 * kk + 8 * (l >> 4));
+    const float bias3 = (l & 15) < NOUT ? N.master[OFF_B3 + (l & 15)] : 0.f;
+
+    // gather role: eight threads per cell; thread (r, pc, hb) loads rows 2hb, 2hb+1 of patch plane pc
+    const int r = t >> 3, pc = (t >> 1) & 3, hb = t & 1;
+    const uint64_t ncell = (uint64_t)g.nx * g.ny * g.nz;
+    auto cell_of = [&](int64_t tile) -> uint64_t {
+        const int64_t s = tile * TM + r;
+        const uint64_t c = (tile < ntiles && s < n) ? cells[s] : 0;
+        return c < ncell ? c : 0;
+    };
+    float2 v[8];
+    auto fetch = [&](uint64_t cell) {
+        int i, j, k;
+        cell_xyz(cell, g, i, j, k);
+        const int kk = wrapc(k + pc - 1, g.nz, g.pz);
+        const uint64_t nx = (uint64_t)g.nx;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
-                    const int ii = wrapc(i + cl[0] + dx, g.nx, g.px), jj = wrapc(j + cl[1] + dy, g.ny, g.py);
-                    const int kk = wrapc(k + cl[2] + dz, g.nz, g.pz);
-                    const float2 v = g.psi[(uint64_t)ii + (uint64_t)g.nx * ((uint64_t)jj + (uint64_t)g.ny * kk)];
-                    const float wgt = (dx ? u[0] : 1.f - u[0]) * (dy ? u[1] : 1.f - u[1]) * (dz ? u[2] : 1.f - u[2]);
-                    re += wgt * v.x;
-                    im += wgt * v.y;
-                }
-                o.cell = cell;
-                o.off[0] = x;
-                o.off[1] = y;
-                o.off[2] = z;
-                o.rho = re * re + im * im;
-                o.iters = 0;
-                o.status = (uint16_t)(VX_SAMPLE_SURROGATE | (np >= 4 ? VX_SAMPLE_MULTI : 0));
-                out[s] = o;
+        for (int b = 0; b < 2; ++b) {
+            const int jj = wrapc(j + 2 * hb + b - 1, g.ny, g.py);
+            const float2 *row = g.psi + nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
+        }
+    };
+    int64_t tile = blockIdx.x;
+    fetch(cell_of(tile));
+    uint64_t cell_next = cell_of(tile + G);
+    for (; tile < ntiles; tile += G) {
+        lds_barrier();  // the previous tile is finished with sX, sH and sOut (and the table is loaded)
+        {
+            float ss = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ss += v[q].x * v[q].x + v[q].y * v[q].y;
+            ss += __shfl_xor(ss, 1);
+            ss += __shfl_xor(ss, 2);
+            ss += __shfl_xor(ss, 4);
+            const float is = 1.f / (ss > 0.f ? sqrtf(ss * (1.f / 64.f)) : 1.f);
+            __bf16 *dst = sX + r * XP + 32 * pc + 16 * hb;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                dst[2 * q] = (__bf16)(v[q].x * is);
+                dst[2 * q + 1] = (__bf16)(v[q].y * is);
             }
         }
-        // queue the rest: one atomic per wavefront
-        const uint64_t qm = __ballot(queue);
-        if (qm) {
-            unsigned long long base = 0;
-            if (t == __builtin_ctzll(qm)) base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
-            base = __shfl(base, __builtin_ctzll(qm));
-            if (queue) {
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-                const int64_t k = (int64_t)base + rank;
-                fb_cell[k] = cell;
-                fb_desc[k] = (uint16_t)d;
-                fb_index[k] = s;
+        // next tile's nodes and the ids of the one after, in flight while this tile's layers run
+        fetch(cell_next);
+        cell_next = cell_of(tile + 2 * G);
+        lds_barrier();
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[rr][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < NK1; ++kk) {
+            bf16x8 a[4];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) a[rr] = ld8(sX + (16 * rr + (l & 15)) * XP + 32 * kk + 8 * (l >> 4));
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(a[rr], b1[c][kk], acc[rr][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    sH[(16 * rr + 4 * (l >> 4) + i) * HP + n0 + 16 * c + (l & 15)] =
+                        (__bf16)tab(sg, acc[rr][c][i] + bias1[c], 0);
+        lds_barrier();
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[rr][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < NK2; ++kk) {
+            bf16x8 a[4];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) a[rr] = ld8(sH + (16 * rr + (l & 15)) * HP + 32 * kk + 8 * (l >> 4));
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(a[rr], b2[c][kk], acc[rr][c]);
+        }
+        lds_barrier();  // every wavefront has read H1
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    sH[(16 * rr + 4 * (l >> 4) + i) * HP + n0 + 16 * c + (l & 15)] =
+                        (__bf16)tab(sg, acc[rr][c][i] + bias2[c], 0);
+        lds_barrier();
+        if (headw) {
+            f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < NK2; ++kk)
+                z = mfma(ld8(sH + (16 * w + (l & 15)) * HP + 32 * kk + 8 * (l >> 4)), b3[kk], z);
+            if ((l & 15) < NOUT) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sOut[(16 * w + 4 * (l >> 4) + i) * NOUT + (l & 15)] = z[i] + bias3;
             }
+        }
+        lds_barrier();
+        if (t < TM && tile * TM + t < n) {
+            const float *o = sOut + t * NOUT;
+            net_out[tile * TM + t] = make_float4(o[0], o[1], o[2], 1.f / (1.f + expf(-o[3])));
+        }
+    }
+}
+
+// Inference, part 2: one thread per listed cell. Confident single-core interior cells get the
+// network's point polished by one Newton step; the others, and cells whose polish fails, are queued
+// (cell, descriptor, position in the list) for the plain refinement, with one atomic per wavefront.
+__global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict__ cells,
+                                               const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
+                                               int64_t cap, const float4 *__restrict__ net_out, float thr,
+                                               vx_sample *out, uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
+                                               int64_t *fb_count) {
+    const int64_t n = min(*count, cap);
+    if ((int64_t)blockIdx.x * NT >= n) return;  // uniform per workgroup
+    const int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x;
+    bool queue = false;
+    uint64_t cell = 0;
+    uint32_t d = 0;
+    if (s < n) {
+        cell = cells[s];
+        d = desc[s];
+        float x0, y0, z0;
+        int np;
+        first_estimate(d, x0, y0, z0, np);
+        const float4 o = net_out[s];
+        bool mine = np == 2 && o.w >= thr && cell < (uint64_t)g.nx * g.ny * g.nz;
+        int i = 0, j = 0, k = 0;
+        if (mine) {
+            cell_xyz(cell, g, i, j, k);
+            mine = interior(g, i, j, k);
+        }
+        if (mine) {
+            const float x0v[3] = {x0, y0, z0};
+            const float xs[3] = {x0 + o.x, y0 + o.y, z0 + o.z};
+            float x[3], rho = 0.f;
+            mine = polish(g, i, j, k, x0v, xs, x, rho);
+            if (mine) {
+                vx_sample r{};
+                r.cell = cell;
+                r.off[0] = x[0];
+                r.off[1] = x[1];
+                r.off[2] = x[2];
+                r.rho = rho;
+                r.iters = 1;
+                r.status = (uint16_t)VX_SAMPLE_SURROGATE;
+                out[s] = r;
+            }
+        }
+        queue = !mine;
+    }
+    const uint64_t qm = __ballot(queue);
+    if (qm) {
+        const int lead = __builtin_ctzll(qm);
+        unsigned long long base = 0;
+        if ((int)(threadIdx.x & 63) == lead) base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
+        base = ((unsigned long long)(uint32_t)__shfl((int)(base >> 32), lead) << 32) | (uint32_t)__shfl((int)base, lead);
+        if (queue) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+            const int64_t k = (int64_t)base + rank;
+            fb_cell[k] = cell;
+            fb_desc[k] = (uint16_t)d;
+            fb_index[k] = s;
         }
     }
 }
@@ -717,6 +924,7 @@ struct vx_mlp {
     float *dZ3 = nullptr, *loss = nullptr;
     // inference fallback queue (grown on demand)
     int64_t fb_cap = 0;
+    float4 *net_out = nullptr;
     uint64_t *fb_cell = nullptr;
     uint16_t *fb_desc = nullptr;
     int64_t *fb_index = nullptr;
@@ -994,7 +1202,7 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     if (vx_status st = vx_check_refine_params(h, prm)) return st;
     if (vx_status st = vx_bind(h)) return st;
     if (cap > m->fb_cap) {  // fallback queue sized for the whole list
-        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index}) {
+        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index, (void *)m->net_out}) {
             if (!q) continue;
             (void)hipFree(q);
             for (auto &a : m->allocs)
@@ -1003,8 +1211,10 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
         m->fb_cell = nullptr;
         m->fb_desc = nullptr;
         m->fb_index = nullptr;
+        m->net_out = nullptr;
         m->fb_cap = 0;
         vx_status st = dalloc(m, (void **)&m->fb_cell, (size_t)cap * 8);
+        if (st == VX_OK) st = dalloc(m, (void **)&m->net_out, (size_t)cap * sizeof(float4));
         if (st == VX_OK) st = dalloc(m, (void **)&m->fb_desc, (size_t)cap * 2);
         if (st == VX_OK) st = dalloc(m, (void **)&m->fb_index, (size_t)cap * 8);
         if (st) return st;
@@ -1013,11 +1223,17 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     hipStream_t hs = (hipStream_t)s;
     vx_timer tm(h, hs, VX_KIND_MLP);
     hipLaunchKernelGGL(zero_i64_k, dim3(1), dim3(1), 0, hs, m->fb_count);
-    hipLaunchKernelGGL(infer_k, dim3((unsigned)((cap + TM - 1) / TM)), dim3(NT), 0, hs, net_of(m), geo_of(dims, d_psi),
-                       d_cells, d_cell_desc, d_count, cap, conf_threshold, d_out, m->fb_cell, m->fb_desc, m->fb_index,
-                       m->fb_count);
+    const int64_t tiles = (cap + TM - 1) / TM;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, h->num_cu > 0 ? h->num_cu : 256));
+    hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
+                       d_count, cap, m->net_out);
     tm.stop();
-    vx_status st = vx_hip_check(h, hipGetLastError(), "infer_k launch");
+    vx_timer tp(h, hs, VX_KIND_POLISH);
+    hipLaunchKernelGGL(polish_k, dim3((unsigned)((cap + NT - 1) / NT)), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
+                       d_cell_desc, d_count, cap, (const float4 *)m->net_out, conf_threshold, d_out, m->fb_cell,
+                       m->fb_desc, m->fb_index, m->fb_count);
+    tp.stop();
+    vx_status st = vx_hip_check(h, hipGetLastError(), "surrogate inference launch");
     if (st) return st;
     return vx_refine_launch(h, dims, d_psi, m->fb_cell, m->fb_desc, nullptr, m->fb_count, cap, prm, d_out, hs,
                             m->fb_index);

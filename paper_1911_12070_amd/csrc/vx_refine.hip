@@ -127,6 +127,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     } else {
         n_items = min(*A.count, A.cap);
     }
+    // chunk size: REF_CHUNK, or down to 8 samples when the list is short for the grid, so that a
+    // short list (a surrogate's fallback cells, say) still spreads over many wavefronts
+    const int64_t chunk = BATCH ? REF_CHUNK : max((int64_t)8, min((int64_t)REF_CHUNK, (n_items + nwaves - 1) / nwaves));
     // samples [next, end) of frame cf are this wave's unclaimed ones (uniform); chunk w is wave w's
     // first, the rest are handed out in order by the chunk counter
     int cf = 0;
@@ -149,12 +152,16 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             next = (ci - s_cstart[lo]) * REF_CHUNK;
             end = min(s_items[lo], next + REF_CHUNK);
         } else {
-            next = min(n_items, ci * REF_CHUNK);
-            end = min(n_items, next + REF_CHUNK);
+            next = min(n_items, ci * chunk);
+            end = min(n_items, next + chunk);
             more = next < end;
         }
     };
     claim(wave);
+    // chunks beyond the first one per wavefront exist only if the list has more chunks than there
+    // are wavefronts; otherwise nobody touches the counter
+    if constexpr (BATCH) more = more && s_cstart[nframes] > nwaves;
+    else more = more && (n_items + chunk - 1) / chunk > nwaves;
 
     int phase = PH_IDLE, mode = MODE_DESCENT;
     int fr = 0;  // frame of this lane's sample

@@ -222,14 +222,24 @@ def test_infer_fallback_and_surrogate(ex, tmp_path):
     b = samples_to_numpy(res, nc)
     fo = fo.cpu().numpy()
     cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    cells = out["cells"][:nc].cpu().numpy()
     sur = (b["status"] & SAMPLE_SURROGATE) != 0
     npierced = np.array([bin(int(v) & 0x555 | (int(v) >> 1) & 0x555).count("1") for v in cdesc])
-    log(f"threshold 0: {sur.sum()} of {nc} cells from the surrogate")
-    assert np.array_equal(sur, npierced == 2)
-    for i in np.nonzero(sur)[0][:500]:
-        x0 = M.first_estimate(int(cdesc[i])).astype(np.float32)
-        assert np.array_equal(b["off"][i], (x0 + fo[i, :3]).astype(np.float32))
-        assert b["iters"][i] == 0
+    log(f"threshold 0: {sur.sum()} of {nc} cells from the surrogate ({(npierced == 2).sum()} eligible)")
+    assert not (sur & (npierced != 2)).any()
+    assert sur.sum() >= 0.9 * (npierced == 2).sum()
+    # each surrogate sample is the oracle's polish of the network point (FP32 vs FP64 arithmetic)
+    worst = 0.0
+    for i in np.nonzero(sur)[0][:400]:
+        x0 = M.first_estimate(int(cdesc[i]))
+        re, im = oracle.gather_patch(psi_np, int(cells[i]))
+        start = x0.astype(np.float32) + fo[i, :3]
+        ref = M.polish(re, im, int(cdesc[i]), start.astype(np.float64))
+        assert ref is not None
+        worst = max(worst, float(np.abs(b["off"][i] - ref[0]).max()))
+        assert b["iters"][i] == 1
+    log(f"polish: worst difference from the oracle {worst:.2e}")
+    assert worst < 1e-4
     assert b[~sur].tobytes() == plain[~sur].tobytes()
     path = str(tmp_path / "w.bin")
     vx_mlp_save(ex.h, m, path)

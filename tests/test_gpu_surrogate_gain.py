@@ -1,0 +1,100 @@
+"""What the trained surrogate gains over the method without it, on a fresh-seed field it never saw
+(512^3, 2048 waves, |n| in [6, 16], seed 5).
+
+Three paths produce a core sample for every listed cell, and the plain refinement (descent +
+Newton polish, Sec. 3.3.3 reading) is the judge of the other two:
+  * plain     -- vx_refine;
+  * untrained -- the inference path with a zero network (every eligible cell polished by one
+                 Newton step from the first estimate x0): the surrogate path without the network;
+  * trained   -- the committed trained network: one Newton step from its point, fallback below
+                 confidence 0.9.
+The trained path must keep the median position error at or below 0.02 cell, and the network must
+do better than the first estimate as a starting point: more eligible cells within 0.02 cell after
+the same one Newton step. Speeds (HIP events) and the fallback fraction are printed for the record.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import vxinputs
+
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_1911_12070_amd", "weights", "surrogate_c2.bin")
+
+
+def test_trained_surrogate_gain():
+    import torch
+    from paper_1911_12070_amd import (KIND_MLP, KIND_POLISH, KIND_REFINE, SAMPLE_SURROGATE, Extractor, dims,
+                                      samples_to_numpy, vx_mlp_create, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
+                                      vx_profile_enable, vx_profile_read)
+    ex = Extractor(0)
+    psi = ex.gen_tangle(vxinputs.tangle_512())
+    nz, ny, nx = psi.shape
+    d = dims(nx, ny, nz, 7)
+    n_all = nx * ny * nz
+    out = ex.alloc_winding(psi.shape, face_cap=n_all // 16, cell_cap=n_all // 16, wind=False)
+    ex.winding(psi, 7, out)
+    torch.cuda.synchronize()
+    nc = int(out["counts"][1])
+    cap = out["cells"].numel()
+    cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    npierced = np.array([bin(int(v) & 0x555 | (int(v) >> 1) & 0x555).count("1") for v in cdesc])
+
+    def run(fn, kinds, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        vx_profile_enable(ex.h, True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        ms = sum(vx_profile_read(ex.h, k)[0] for k in kinds) / reps
+        vx_profile_enable(ex.h, False)
+        return ms
+
+    plain = ex.alloc_samples(cap)
+    t_plain = run(lambda: ex.refine(psi, out, 7, plain), [KIND_REFINE])
+    P = samples_to_numpy(plain, nc)
+    good = (P["status"] & (8 | 16 | 32 | 64)) == 0
+
+    zero = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    z = ex.alloc_samples(cap)
+    vx_mlp_infer(ex.h, zero, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, z)
+    trained = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    vx_mlp_load(ex.h, trained, WEIGHTS)
+    a = ex.alloc_samples(cap)
+    vx_mlp_infer(ex.h, trained, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, a)
+    b = ex.alloc_samples(cap)
+    t_sur = run(lambda: vx_mlp_infer(ex.h, trained, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.9, b),
+                [KIND_MLP, KIND_POLISH, KIND_REFINE])
+    torch.cuda.synchronize()
+    Z, A, B = samples_to_numpy(z, nc), samples_to_numpy(a, nc), samples_to_numpy(b, nc)
+
+    def err(S):
+        return np.abs(S["off"].astype(np.float64) - P["off"].astype(np.float64)).max(axis=1)
+
+    elig = (npierced == 2) & good
+    ez, ea, eb = err(Z), err(A), err(B)
+    # every eligible cell through the same one Newton step: from x0 (untrained) or from the network's point
+    within_z = float(np.mean(ez[elig] < 0.02))
+    within_a = float(np.mean(ea[elig] < 0.02))
+    sur = (B["status"] & SAMPLE_SURROGATE) != 0
+    log(f"cells {nc}, eligible {elig.sum()}")
+    log(f"one Newton step from x0      : within 0.02 {within_z:.5f}, median {np.median(ez[elig]):.2e}, "
+        f"p99 {np.percentile(ez[elig], 99):.2e}")
+    log(f"one Newton step from network : within 0.02 {within_a:.5f}, median {np.median(ea[elig]):.2e}, "
+        f"p99 {np.percentile(ea[elig], 99):.2e}")
+    log(f"trained path, threshold 0.9  : surrogate {sur.mean():.4f}, median err all {np.median(eb[good]):.2e}, "
+        f"surrogate cells median {np.median(eb[sur & good]):.2e} p99 {np.percentile(eb[sur & good], 99):.2e}")
+    log(f"kernel time: plain {t_plain:.3f} ms ({nc / t_plain / 1e6:.3f} G samples/s), surrogate path {t_sur:.3f} ms "
+        f"({nc / t_sur / 1e6:.3f} G samples/s)")
+    assert np.median(eb[good]) <= 0.02
+    assert np.median(eb[sur & good]) <= 0.02
+    assert sur.mean() > 0.9
+    assert within_a > within_z, "the network must improve on the first estimate as the Newton start"
+    vx_mlp_destroy(ex.h, zero)
+    vx_mlp_destroy(ex.h, trained)
+    ex.close()

@@ -108,3 +108,33 @@ def test_bf16_rounding():
     x = np.random.default_rng(9).normal(size=10000) * np.exp(np.random.default_rng(10).uniform(-20, 20, 10000))
     ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
     assert np.array_equal(M.bf16(x), ref)
+
+
+def test_polish_linear_field_lands_on_the_line():
+    """For linear psi = a.(x-p) + i b.(x-p) the trilinear patch is exact and one Newton step from any
+    point of the plane reaches the plane's intersection with the nodal line p + s (a x b)."""
+    rng = np.random.default_rng(21)
+    for trial in range(20):
+        a, b = rng.normal(size=3), rng.normal(size=3)
+        p = rng.uniform(0.2, 0.8, 3)
+        idx = np.arange(4) - 1.0
+        zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+        X = np.stack([xx, yy, zz], -1) - p
+        re, im = X @ a, X @ b
+        desc = 0b01 | 0b11 << 2  # -x and +x faces: x0 = cell centre
+        start = np.array([0.5, 0.5, 0.5]) + rng.normal(0, 0.3, 3)
+        res = M.polish(re, im, desc, start)
+        assert res is not None
+        x, rho = res
+        t = np.cross(a, b)
+        t /= np.linalg.norm(t)
+        # on the nodal line, and in the plane through x0 normal to t
+        assert abs(a @ (x - p)) < 1e-12 and abs(b @ (x - p)) < 1e-12
+        assert abs((x - np.array([0.5, 0.5, 0.5])) @ t) < 1e-12
+        assert rho < 1e-24
+
+
+def test_polish_degenerate_cases():
+    re = np.zeros((4, 4, 4))
+    im = np.zeros((4, 4, 4))
+    assert M.polish(re, im, 0b01 | 0b11 << 2, [0.5, 0.5, 0.5]) is None  # no pseudo-vorticity
