@@ -56,7 +56,7 @@ typedef enum {
     VX_ERR_CAPACITY = -2,    /* an output list was too small (true counts were still written) */
     VX_ERR_DEVICE = -3,      /* a HIP call failed */
     VX_ERR_NOMEM = -4,       /* host or device allocation failed */
-    VX_ERR_UNSUPPORTED = -5  /* valid request outside what this build supports */
+    VX_ERR_UNSUPPORTED = -5  /* valid request outside what the library supports */
 } vx_status;
 
 typedef struct vx_handle vx_handle;
@@ -190,7 +190,8 @@ vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_
 
 /* ------------------------------------------------------------------------------------------
  * Learned surrogate of the refinement (an extension of the method; the plain refinement above
- * labels its training data, judges its error and takes over below a confidence threshold).
+ * labels its training data, is the reference for its error and takes over below a confidence
+ * threshold).
  *
  * Network: inputs f (128) from the 4x4x4 patch of nodes around a cell (offsets -1..2 on each
  * axis from the min corner; patch node q = a + 4b + 16c, x fastest): f[2q] = Re psi_q / s,

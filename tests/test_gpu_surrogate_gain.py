@@ -2,7 +2,7 @@
 (512^3, 2048 waves, |n| in [6, 16], seed 5).
 
 Three paths produce a core sample for every listed cell, and the plain refinement (descent +
-Newton polish, Sec. 3.3.3 reading) is the judge of the other two:
+Newton polish, Sec. 3.3.3 reading) is the reference for the other two:
   * plain     -- vx_refine;
   * untrained -- the inference path with a zero network (every eligible cell polished by one
                  Newton step from the first estimate x0): the surrogate path without the network;
