@@ -53,14 +53,16 @@ __device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f3
 }
 __device__ __forceinline__ bf16x8 ld8(const __bf16 *p) { return *(const bf16x8 *)p; }
 
-// gelu (kind 0) or its derivative (kind 1) from a table of (value, next - value) at GLO + i / GSC
+// gelu (kind 0) or its derivative (kind 1) from a table of (value, next - value) at GLO + i / GSC.
+// No conditionals, so that the lookups of a whole epilogue can be in flight together: the argument
+// is clamped to the table's range, whose ends hold gelu(-8) = 0, gelu(8) = 8, gelu'(-8) = 0 and
+// gelu'(8) = 1 to FP32 precision, and gelu(x) = x beyond 8 is restored by adding max(x - 8, 0).
 __device__ __forceinline__ float tab(const float2 *t, float x, int kind) {
-    if (x >= GHI) return kind ? 1.f : x;
-    if (x <= GLO) return 0.f;
-    const float u = (x - GLO) * GSC;
+    const float u = (fminf(fmaxf(x, GLO), GHI) - GLO) * GSC;
     const int i = min((int)u, GT - 1);
     const float2 e = t[i];
-    return e.x + (u - (float)i) * e.y;
+    const float v = e.x + (u - (float)i) * e.y;
+    return kind ? v : v + fmaxf(x - GHI, 0.f);
 }
 
 struct Geo {
@@ -69,9 +71,8 @@ struct Geo {
 };
 
 __device__ __forceinline__ int wrapc(int q, int n, int per) {
-    if (q < 0) return per ? q + n : 0;
-    if (q >= n) return per ? q - n : n - 1;
-    return q;
+    const int below = per ? q + n : 0, above = per ? q - n : n - 1;
+    return q < 0 ? below : (q >= n ? above : q);
 }
 
 // cell id -> node coordinates (cells of any grid that fits in memory, < 2^53)
