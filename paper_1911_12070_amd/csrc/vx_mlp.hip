@@ -45,24 +45,31 @@ constexpr int NT = 256;          // threads per workgroup
 constexpr int XP = NIN + 8;      // LDS row pitch (values) of the input tile
 constexpr int HP = NH + 8;       // LDS row pitch of a hidden tile
 constexpr int GT = 1024;         // table intervals on [-8, 8]
-constexpr float GLO = -8.f, GHI = 8.f, GSC = 64.f;
+constexpr float GLO = -8.f, GSC = 64.f;   // table on [GLO, GLO + GT / GSC] = [-8, 8]
 constexpr int WCH = 512;         // rows per chunk of the weight-gradient kernel
 
 __device__ __forceinline__ f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ bf16x8 ld8(const __bf16 *p) { return *(const bf16x8 *)p; }
+// two floats as bfloat16 (round to nearest even) in one word, the first in the low half; one
+// v_cvt_pk_bf16_f32
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 h2v __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){a, b}, h2v));
+}
 
-// gelu (kind 0) or its derivative (kind 1) from a table of (value, next - value) at GLO + i / GSC.
-// No conditionals, so that the lookups of a whole epilogue can be in flight together: the argument
-// is clamped to the table's range, whose ends hold gelu(-8) = 0, gelu(8) = 8, gelu'(-8) = 0 and
-// gelu'(8) = 1 to FP32 precision, and gelu(x) = x beyond 8 is restored by adding max(x - 8, 0).
-__device__ __forceinline__ float tab(const float2 *t, float x, int kind) {
-    const float u = (fminf(fmaxf(x, GLO), GHI) - GLO) * GSC;
-    const int i = min((int)u, GT - 1);
-    const float2 e = t[i];
-    const float v = e.x + (u - (float)i) * e.y;
-    return kind ? v : v + fmaxf(x - GHI, 0.f);
+// gelu or its derivative, piecewise linear in the table coordinate u = (x - GLO) GSC: segment i
+// (u in [i, i + 1]) is stored as (intercept, slope), f = intercept + u slope. No conditionals, so
+// that the lookups of a whole epilogue can be in flight together. Outside [-8, 8] the end segments
+// continue linearly; their slopes are those of gelu (0 and 1) and of gelu' (0 and 0) there to FP32
+// precision, so gelu(x) = x above 8 and gelu' stays 0 or 1. (x - GLO) GSC is one rounding either
+// way, GSC being a power of two.
+__device__ __forceinline__ float tab(const float2 *t, float x) {
+    const float u = fmaf(x, GSC, -GLO * GSC);
+    const float2 e = t[(int)fminf(fmaxf(u, 0.f), (float)(GT - 1))];
+    return fmaf(u, e.y, e.x);
 }
 
 struct Geo {
@@ -315,11 +322,11 @@ __device__ __forceinline__ void hidden(const Net &N, const __bf16 *sX, __bf16 *s
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * r + 4 * (l >> 4) + i;
                 const float z = acc[r][c][i] + bias;
-                const __bf16 hv = (__bf16)tab(sg, z, 0);
+                const __bf16 hv = (__bf16)tab(sg, z);
                 sH[row * HP + col] = hv;
                 if (H1 && row0 + row < nrows) {
                     H1[(row0 + row) * NH + col] = hv;
-                    G1[(row0 + row) * NH + col] = (__bf16)tab(sd, z, 1);
+                    G1[(row0 + row) * NH + col] = (__bf16)tab(sd, z);
                 }
             }
     }
@@ -336,11 +343,11 @@ __device__ __forceinline__ void hidden(const Net &N, const __bf16 *sX, __bf16 *s
             for (int i = 0; i < 4; ++i) {
                 const int row = 16 * r + 4 * (l >> 4) + i;
                 const float z = acc[r][c][i] + bias;
-                const __bf16 hv = (__bf16)tab(sg, z, 0);
+                const __bf16 hv = (__bf16)tab(sg, z);
                 sH[row * HP + col] = hv;
                 if (H2 && row0 + row < nrows) {
                     H2[(row0 + row) * NH + col] = hv;
-                    G2[(row0 + row) * NH + col] = (__bf16)tab(sd, z, 1);
+                    G2[(row0 + row) * NH + col] = (__bf16)tab(sd, z);
                 }
             }
     }
@@ -385,8 +392,9 @@ __global__ void tables_k(float2 *gelu, float2 *dgelu) {
     auto g = [](double x) { return x * 0.5 * (1.0 + erf(x / sqrt(2.0))); };
     auto dg = [](double x) { return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * M_PI); };
     const double x0 = GLO + (double)i / GSC, x1 = GLO + (double)(i + 1) / GSC;
-    gelu[i] = make_float2((float)g(x0), (float)(g(x1) - g(x0)));
-    dgelu[i] = make_float2((float)dg(x0), (float)(dg(x1) - dg(x0)));
+    const double sg = g(x1) - g(x0), sd = dg(x1) - dg(x0);  // slopes per unit of u
+    gelu[i] = make_float2((float)(g(x0) - i * sg), (float)sg);
+    dgelu[i] = make_float2((float)(dg(x0) - i * sd), (float)sd);
 }
 
 // host-layout FP32 parameters -> BF16 operand copies
@@ -697,41 +705,46 @@ constexpr int NTI = 512;                        // inference workgroup: 8 wavefr
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Inference, part 1: the network for every listed cell. Persistent: one workgroup of 8 wavefronts
-// per CU walks the 64-cell tiles; wavefront w owns columns 32w .. 32w+31 of both hidden layers and
-// loads their B operands once (24 16-byte fragments kept in registers for the whole run, plus the
-// head's 8 for the wavefronts that compute it), instead of once per tile; the gelu table is loaded
-// once per workgroup. Small per-wavefront register footprints leave room for two wavefronts per
-// SIMD. The patch nodes of the next tile are requested before the current tile's layers run, the
-// cell ids one tile further ahead; the workgroup synchronises with LDS-only barriers so that those
-// loads stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
+// per CU walks the 64-cell tiles; wavefront w owns features 32w .. 32w+31 of both hidden layers and
+// keeps their B operands in registers for the whole run (24 16-byte fragments) instead of loading
+// them per tile. The layers are computed transposed, (X W)^T = W^T X^T, so that a lane ends with
+// four consecutive features of one cell: they go to LDS as one 8-byte word (first layer) or, after
+// the second layer, straight into a B operand of the head, whose k index is permuted to match
+// (k = 8q + j holds feature 32w + 4q + j for j < 4 and 32w + 16 + 4q + j - 4 otherwise, q = lane / 16).
+// Each wavefront thus multiplies its own 32 features by the matching rows of W3 and the eight
+// partial heads of a cell are summed in LDS: three barriers per tile (features, first layer, head).
+// The barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell
+// ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
                                                    const int64_t *__restrict__ count, int64_t cap, float4 *net_out) {
+    constexpr int NW = NTI / 64;
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
     __shared__ float2 sg[GT];
-    __shared__ float sOut[TM * NOUT];
+    __shared__ __attribute__((aligned(16))) float sB[2 * NH];          // b1 then b2
+    __shared__ __attribute__((aligned(16))) float sP[NW * TM * NOUT];  // partial heads [wavefront][cell][4]
     const int64_t n = min(*count, cap);
     const int64_t ntiles = (n + TM - 1) / TM;
     if ((int64_t)blockIdx.x >= ntiles) return;  // uniform per workgroup
-    const int t = threadIdx.x, l = t & 63, w = t >> 6, n0 = 32 * w;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, n0 = 32 * w, q4 = 4 * (l >> 4);
     const int64_t G = gridDim.x;
     for (int i = t; i < GT; i += NTI) sg[i] = N.gelu[i];
-    bf16x8 b1[2][NK1], b2[2][NK2], b3[NK2];
-    float bias1[2], bias2[2];
+    sB[t] = N.master[t < NH ? OFF_B1 + t : OFF_B2 + t - NH];
+    bf16x8 b1[2][NK1], b2[2][NK2], a3;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const int col = n0 + 16 * c + (l & 15);
-        bias1[c] = N.master[OFF_B1 + col];
-        bias2[c] = N.master[OFF_B2 + col];
 #pragma unroll
         for (int kk = 0; kk < NK1; ++kk) b1[c][kk] = ld8(N.w1t + col * NIN + 32 * kk + 8 * (l >> 4));
 #pragma unroll
         for (int kk = 0; kk < NK2; ++kk) b2[c][kk] = ld8(N.w2t + col * NH + 32 * kk + 8 * (l >> 4));
     }
-    const bool headw = w < TM / 16;  // wavefronts 0..3 compute the head for rows 16w .. 16w+15
-#pragma unroll
-    for (int kk = 0; kk < NK2; ++kk) b3[kk] = ld8(N.w3t + (l & 15) * NH + 32 * kk + 8 * (l >> 4));
-    const float bias3 = (l & 15) < NOUT ? N.master[OFF_B3 + (l & 15)] : 0.f;
+    {   // head A operand: row l % 16 of W3^T (rows 4..15 are zero), the permuted k of this wavefront
+        const __bf16 *p = N.w3t + (l & 15) * NH + n0 + q4;
+        const uint2 lo = *(const uint2 *)p, hi = *(const uint2 *)(p + 16);
+        a3 = __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    }
+    const float4 bias3 = make_float4(N.master[OFF_B3], N.master[OFF_B3 + 1], N.master[OFF_B3 + 2], N.master[OFF_B3 + 3]);
 
     // gather role: eight threads per cell; thread (r, pc, hb) loads rows 2hb, 2hb+1 of patch plane pc
     const int r = t >> 3, pc = (t >> 1) & 3, hb = t & 1;
@@ -759,7 +772,7 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
     fetch(cell_of(tile));
     uint64_t cell_next = cell_of(tile + G);
     for (; tile < ntiles; tile += G) {
-        lds_barrier();  // the previous tile is finished with sX, sH and sOut (and the table is loaded)
+        // features -> sX (free: the previous tile's first layer ended before its second barrier)
         {
             float ss = 0.f;
 #pragma unroll
@@ -768,22 +781,22 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
             ss += __shfl_xor(ss, 2);
             ss += __shfl_xor(ss, 4);
             const float is = 1.f / (ss > 0.f ? sqrtf(ss * (1.f / 64.f)) : 1.f);
-            __bf16 *dst = sX + r * XP + 32 * pc + 16 * hb;
+            uint32_t *dst = (uint32_t *)(sX + r * XP + 32 * pc + 16 * hb);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                dst[2 * q] = (__bf16)(v[q].x * is);
-                dst[2 * q + 1] = (__bf16)(v[q].y * is);
-            }
+            for (int q = 0; q < 8; ++q) dst[q] = pack2(v[q].x * is, v[q].y * is);
         }
         // next tile's nodes and the ids of the one after, in flight while this tile's layers run
         fetch(cell_next);
         cell_next = cell_of(tile + 2 * G);
-        lds_barrier();
+        lds_barrier();  // sX complete (and, at the first tile, the table and the biases)
+        // this lane accumulates features n0 + 16c + q4 + 0..3 of cell 16rr + l % 16, from their biases
         f32x4 acc[4][2];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
+        for (int c = 0; c < 2; ++c) {
+            const f32x4 b = *(const f32x4 *)(sB + n0 + 16 * c + q4);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) acc[rr][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int rr = 0; rr < 4; ++rr) acc[rr][c] = b;
+        }
 #pragma unroll
         for (int kk = 0; kk < NK1; ++kk) {
             bf16x8 a[4];
@@ -792,21 +805,23 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(a[rr], b1[c][kk], acc[rr][c]);
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b1[c][kk], a[rr], acc[rr][c]);
         }
+        // sH is free: the previous tile's second layer ended before its last barrier
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
+                *(uint2 *)(sH + (16 * rr + (l & 15)) * HP + n0 + 16 * c + q4) =
+                    make_uint2(pack2(tab(sg, acc[rr][c][0]), tab(sg, acc[rr][c][1])),
+                               pack2(tab(sg, acc[rr][c][2]), tab(sg, acc[rr][c][3])));
+        lds_barrier();  // H1 complete
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    sH[(16 * rr + 4 * (l >> 4) + i) * HP + n0 + 16 * c + (l & 15)] =
-                        (__bf16)tab(sg, acc[rr][c][i] + bias1[c], 0);
-        lds_barrier();
+        for (int c = 0; c < 2; ++c) {
+            const f32x4 b = *(const f32x4 *)(sB + NH + n0 + 16 * c + q4);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) acc[rr][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int rr = 0; rr < 4; ++rr) acc[rr][c] = b;
+        }
 #pragma unroll
         for (int kk = 0; kk < NK2; ++kk) {
             bf16x8 a[4];
@@ -815,32 +830,31 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(a[rr], b2[c][kk], acc[rr][c]);
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b2[c][kk], a[rr], acc[rr][c]);
         }
-        lds_barrier();  // every wavefront has read H1
+        // H2 never leaves registers: partial head of this wavefront's 32 features; lanes 0..15 end
+        // with outputs 0..3 of cell 16rr + l (the rows of the other lanes are the zero padding)
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    sH[(16 * rr + 4 * (l >> 4) + i) * HP + n0 + 16 * c + (l & 15)] =
-                        (__bf16)tab(sg, acc[rr][c][i] + bias2[c], 0);
-        lds_barrier();
-        if (headw) {
-            f32x4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kk = 0; kk < NK2; ++kk)
-                z = mfma(ld8(sH + (16 * w + (l & 15)) * HP + 32 * kk + 8 * (l >> 4)), b3[kk], z);
-            if ((l & 15) < NOUT) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) sOut[(16 * w + 4 * (l >> 4) + i) * NOUT + (l & 15)] = z[i] + bias3;
-            }
+        for (int rr = 0; rr < 4; ++rr) {
+            const uint4 hv = make_uint4(pack2(tab(sg, acc[rr][0][0]), tab(sg, acc[rr][0][1])),
+                                        pack2(tab(sg, acc[rr][0][2]), tab(sg, acc[rr][0][3])),
+                                        pack2(tab(sg, acc[rr][1][0]), tab(sg, acc[rr][1][1])),
+                                        pack2(tab(sg, acc[rr][1][2]), tab(sg, acc[rr][1][3])));
+            const f32x4 z = mfma(a3, __builtin_bit_cast(bf16x8, hv), f32x4{0.f, 0.f, 0.f, 0.f});
+            if (l < 16) *(f32x4 *)(sP + (w * TM + 16 * rr + l) * NOUT) = z;
         }
-        lds_barrier();
+        lds_barrier();  // partial heads complete
         if (t < TM && tile * TM + t < n) {
-            const float *o = sOut + t * NOUT;
-            net_out[tile * TM + t] = make_float4(o[0], o[1], o[2], 1.f / (1.f + expf(-o[3])));
+            float4 o = bias3;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                const float4 p = *(const float4 *)(sP + (u * TM + t) * NOUT);
+                o.x += p.x;
+                o.y += p.y;
+                o.z += p.z;
+                o.w += p.w;
+            }
+            net_out[tile * TM + t] = make_float4(o.x, o.y, o.z, 1.f / (1.f + expf(-o.w)));
         }
     }
 }

@@ -127,9 +127,11 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     } else {
         n_items = min(*A.count, A.cap);
     }
-    // chunk size: REF_CHUNK, or down to 8 samples when the list is short for the grid, so that a
-    // short list (a surrogate's fallback cells, say) still spreads over many wavefronts
-    const int64_t chunk = BATCH ? REF_CHUNK : max((int64_t)8, min((int64_t)REF_CHUNK, (n_items + nwaves - 1) / nwaves));
+    // chunk size: REF_CHUNK, or down to one sample when the list is short for the grid, so that a
+    // short list (a surrogate's fallback cells, say) spreads over as many wavefronts as it can: its
+    // time is then the latency of its slowest sample, and a wavefront with few live lanes runs the
+    // code paths of those lanes only
+    const int64_t chunk = BATCH ? REF_CHUNK : max((int64_t)1, min((int64_t)REF_CHUNK, (n_items + nwaves - 1) / nwaves));
     // samples [next, end) of frame cf are this wave's unclaimed ones (uniform); chunk w is wave w's
     // first, the rest are handed out in order by the chunk counter
     int cf = 0;
