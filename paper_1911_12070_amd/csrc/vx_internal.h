@@ -30,6 +30,7 @@ struct vx_handle {
     int wind_zc = 0;  // planes per z-chunk (0 = chosen from the grid)
     int ref_blocks_per_cu = 0;   // resident refinement workgroups per CU (0 = not yet queried)
     int refb_blocks_per_cu = 0;  // the same for the batched refinement kernel
+    int refs_blocks_per_cu = 0;  // the same for the short-list refinement kernel
     int ref_refill = 8;          // idle lanes a refinement wavefront waits for before claiming samples
     unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter
     std::map<std::array<int, 4>, int> tuned_zc;  // (nx, ny, nz, periodic) -> planes per z-chunk

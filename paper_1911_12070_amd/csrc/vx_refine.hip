@@ -79,6 +79,188 @@ __device__ __forceinline__ uint64_t divmod53(uint64_t n, uint64_t d, double rd, 
     return q;
 }
 
+// ---- arithmetic shared by the refinement kernels (each a forced-inline function, so that every
+// kernel computes the same FP32 expressions and reaches the same bits)
+
+// first estimate (Sec. 3.3.1): mean of the centres of the pierced faces (-x,+x,-y,+y,-z,+z)
+__device__ __forceinline__ V3 first_estimate(uint32_t desc, uint32_t &status) {
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    int npierced = 0;
+#pragma unroll
+    for (int fc = 0; fc < 6; ++fc) {
+        if (dec2(desc, fc) == 0) continue;
+        const int a = fc >> 1;
+        const float side = (float)(fc & 1);
+        sx += a == 0 ? side : 0.5f;
+        sy += a == 1 ? side : 0.5f;
+        sz += a == 2 ? side : 0.5f;
+        ++npierced;
+    }
+    if (npierced >= 4) status |= VX_SAMPLE_MULTI;
+    if (npierced == 0) {
+        status |= VX_SAMPLE_NO_FACES;
+        return v3(0.5f, 0.5f, 0.5f);
+    }
+    const float inv = 1.0f / (float)npierced;
+    return v3(sx * inv, sy * inv, sz * inv);
+}
+
+// patch extent of the cell at node (gi, gj, gk): bit a set if the patch reaches -1 on axis a, bit
+// 3 + a set if it reaches +2 (else it stops at 0 / +1)
+__device__ __forceinline__ uint32_t patch_ext(int gi, int gj, int gk, int nx, int ny, int nz, int px, int py, int pz) {
+    const int g3[3] = {gi, gj, gk};
+    const int n3[3] = {nx, ny, nz};
+    const int p3[3] = {px, py, pz};
+    uint32_t ext = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (p3[a] || g3[a] - 1 >= 0) ext |= 1u << a;
+        if (p3[a] || g3[a] + 2 < n3[a]) ext |= 8u << a;
+    }
+    return ext;
+}
+
+// the patch cell that holds point x (clamped to the patch) and the local coordinates in it;
+// returns the cell's code (cx+1) + 4 (cy+1) + 16 (cz+1)
+__device__ __forceinline__ int locate(const V3 &x, uint32_t ext, int c[3], float u[3]) {
+    const float xs[3] = {x.x, x.y, x.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int lo = (ext >> a) & 1u ? -1 : 0, hi = (ext >> (3 + a)) & 1u ? 1 : 0;
+        int fl = (int)floorf(xs[a]);
+        fl = max(lo, min(fl, hi));
+        c[a] = fl;
+        u[a] = xs[a] - (float)fl;
+    }
+    return (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
+}
+
+// the 8 nodes of patch cell c of the sample cell at node (gi, gj, gk); corner d = dx + 2 dy + 4 dz
+__device__ __forceinline__ void fetch_corners(const float2 *psi_p, int fnx, int fny, int fnz, int fpx, int fpy,
+                                              int fpz, int gi, int gj, int gk, const int c[3], float2 v[8]) {
+    const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
+    const int64_t i0 = wrap((int64_t)gi + c[0], fnx, fpx);
+    const int64_t i1 = wrap((int64_t)gi + c[0] + 1, fnx, fpx);
+    const int64_t j0 = wrap((int64_t)gj + c[1], fny, fpy);
+    const int64_t j1 = wrap((int64_t)gj + c[1] + 1, fny, fpy);
+    const int64_t k0 = wrap((int64_t)gk + c[2], fnz, fpz);
+    const int64_t k1 = wrap((int64_t)gk + c[2] + 1, fnz, fpz);
+    const float2 *r00 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
+    const float2 *r10 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
+    const float2 *r01 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
+    const float2 *r11 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k1;
+    v[0] = r00[i0];
+    v[1] = r00[i1];
+    v[2] = r10[i0];
+    v[3] = r10[i1];
+    v[4] = r01[i0];
+    v[5] = r01[i1];
+    v[6] = r11[i0];
+    v[7] = r11[i1];
+}
+
+// trilinear psi and its gradient (cell units) at local coordinates u of a cell with corners v
+__device__ __forceinline__ void trilinear(const float2 v[8], const float u[3], float &tr, float &ti, V3 &tgr,
+                                          V3 &tgi) {
+    const float ux = u[0], uy = u[1], uz = u[2];
+    const float mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
+    const float2 a00 = make_float2(mx * v[0].x + ux * v[1].x, mx * v[0].y + ux * v[1].y);
+    const float2 a10 = make_float2(mx * v[2].x + ux * v[3].x, mx * v[2].y + ux * v[3].y);
+    const float2 a01 = make_float2(mx * v[4].x + ux * v[5].x, mx * v[4].y + ux * v[5].y);
+    const float2 a11 = make_float2(mx * v[6].x + ux * v[7].x, mx * v[6].y + ux * v[7].y);
+    const float2 d00 = make_float2(v[1].x - v[0].x, v[1].y - v[0].y);
+    const float2 d10 = make_float2(v[3].x - v[2].x, v[3].y - v[2].y);
+    const float2 d01 = make_float2(v[5].x - v[4].x, v[5].y - v[4].y);
+    const float2 d11 = make_float2(v[7].x - v[6].x, v[7].y - v[6].y);
+    const float2 b0 = make_float2(my * a00.x + uy * a10.x, my * a00.y + uy * a10.y);
+    const float2 b1 = make_float2(my * a01.x + uy * a11.x, my * a01.y + uy * a11.y);
+    tr = mz * b0.x + uz * b1.x;
+    ti = mz * b0.y + uz * b1.y;
+    tgr.z = b1.x - b0.x;
+    tgi.z = b1.y - b0.y;
+    const float2 ey0 = make_float2(a10.x - a00.x, a10.y - a00.y);
+    const float2 ey1 = make_float2(a11.x - a01.x, a11.y - a01.y);
+    tgr.y = mz * ey0.x + uz * ey1.x;
+    tgi.y = mz * ey0.y + uz * ey1.y;
+    const float2 ex0 = make_float2(my * d00.x + uy * d10.x, my * d00.y + uy * d10.y);
+    const float2 ex1 = make_float2(my * d01.x + uy * d11.x, my * d01.y + uy * d11.y);
+    tgr.x = mz * ex0.x + uz * ex1.x;
+    tgi.x = mz * ex0.y + uz * ex1.y;
+}
+
+// orthonormal basis (e1, e2) of the plane normal to the pseudo-vorticity Re grad psi x Im grad psi
+// at x0; a degenerate cross product falls back to the net face flux, then to one pierced face
+__device__ __forceinline__ void plane_basis(const V3 &tgr, const V3 &tgi, uint32_t desc, V3 &e1, V3 &e2,
+                                            uint32_t &status) {
+    V3 t = crs(tgr, tgi);
+    float tn = nrm(t);
+    if (!(tn > 1e-6f * nrm(tgr) * nrm(tgi)) || tn == 0.f) {
+        status |= VX_SAMPLE_TANGENT_FALLBACK;
+        t = v3((float)(dec2(desc, 0) + dec2(desc, 1)), (float)(dec2(desc, 2) + dec2(desc, 3)),
+               (float)(dec2(desc, 4) + dec2(desc, 5)));
+        if (nrm(t) == 0.f) {
+            t = v3(0.f, 0.f, 1.f);
+            for (int fc = 0; fc < 6; ++fc) {
+                const int w = dec2(desc, fc);
+                if (w != 0) {
+                    const int a = fc >> 1;
+                    t = v3(a == 0 ? (float)w : 0.f, a == 1 ? (float)w : 0.f, a == 2 ? (float)w : 0.f);
+                    break;
+                }
+            }
+        }
+        tn = nrm(t);
+    }
+    const float itn = rcp(tn);
+    t = v3(t.x * itn, t.y * itn, t.z * itn);
+    int ax = 0;
+    if (fabsf(t.y) < fabsf(comp(t, ax))) ax = 1;
+    if (fabsf(t.z) < fabsf(comp(t, ax))) ax = 2;
+    e1 = crs(t, v3(ax == 0 ? 1.f : 0.f, ax == 1 ? 1.f : 0.f, ax == 2 ? 1.f : 0.f));
+    const float in1 = rsq(dot(e1, e1));
+    e1 = v3(e1.x * in1, e1.y * in1, e1.z * in1);
+    e2 = crs(t, e1);
+}
+
+// the point x0 + y1 e1 + y2 e2
+__device__ __forceinline__ V3 plane_point(const V3 &x0, const V3 &e1, const V3 &e2, float y1, float y2) {
+    return v3(x0.x + y1 * e1.x + y2 * e2.x, x0.y + y1 * e1.y + y2 * e2.y, x0.z + y1 * e1.z + y2 * e2.z);
+}
+
+__device__ __forceinline__ bool in_patch(const V3 &x, uint32_t ext) {
+    const float lx = (ext & 1u) ? -1.f : 0.f, ly = (ext & 2u) ? -1.f : 0.f;
+    const float lz = (ext & 4u) ? -1.f : 0.f, hx = (ext & 8u) ? 2.f : 1.f;
+    const float hy = (ext & 16u) ? 2.f : 1.f, hz = (ext & 32u) ? 2.f : 1.f;
+    return x.x >= lx && x.x <= hx && x.y >= ly && x.y <= hy && x.z >= lz && x.z <= hz;
+}
+
+// steepest descent of |psi|^2 in the plane: direction (n1, n2) * den = -g / |g|, gn = |g|
+__device__ __forceinline__ bool descent_dir(float vr, float vi, const V3 &gr, const V3 &gim, const V3 &e1,
+                                            const V3 &e2, float &n1, float &n2, float &den, float &gn) {
+    const V3 G = v3(2.f * (vr * gr.x + vi * gim.x), 2.f * (vr * gr.y + vi * gim.y), 2.f * (vr * gr.z + vi * gim.z));
+    const float g1 = dot(e1, G), g2 = dot(e2, G);
+    const float gg = g1 * g1 + g2 * g2;
+    const float ig = rsq(gg);
+    gn = gg * ig;
+    n1 = -g1;
+    n2 = -g2;
+    den = ig;
+    return gg > 0.f && ig < INFINITY;
+}
+
+// Newton step for (Re psi, Im psi) = 0 in the plane: direction (n1, n2) * den = -J^-1 psi
+__device__ __forceinline__ bool newton_dir(float vr, float vi, const V3 &gr, const V3 &gim, const V3 &e1,
+                                           const V3 &e2, float &n1, float &n2, float &den) {
+    const float j00 = dot(e1, gr), j01 = dot(e2, gr);
+    const float j10 = dot(e1, gim), j11 = dot(e2, gim);
+    const float det = j00 * j11 - j01 * j10;
+    const float idet = rcp(det);
+    n1 = -(j11 * vr - j01 * vi);
+    n2 = -(-j10 * vr + j00 * vi);
+    den = idet;
+    return det != 0.f && fabsf(idet) < INFINITY;
+}
+
 // lane phases
 constexpr int PH_IDLE = 0;     // no sample
 constexpr int PH_INIT = 1;     // pending evaluation at the first estimate x0
@@ -93,7 +275,7 @@ constexpr int MODE_NEWTON = 1;   // Newton on (Re psi, Im psi), halving until |p
 // looks up its own sample's frame where the frame matters (corner fetch, output).
 template <bool BATCH>
 __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_frame *frames, int nframes,
-                                                        int refill_min) {
+                                                        int refill_min, int64_t skip_upto) {
     // corner cache: corner d (index dx + 2 dy + 4 dz) of the cell cached by thread t at [d][t]
     __shared__ float2 s_corner[8][REF_THREADS];
     constexpr int NF = BATCH ? VX_BATCH_MAX_FRAMES : 1;
@@ -126,6 +308,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         }
     } else {
         n_items = min(*A.count, A.cap);
+        if (n_items <= skip_upto) return;  // a short list, refined by refine_spec_k (uniform)
     }
     // chunk size: REF_CHUNK, or down to one sample when the list is short for the grid, so that a
     // short list (a surrogate's fallback cells, say) spreads over as many wavefronts as it can: its
@@ -239,42 +422,14 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                         gk = (int)divmod53(cell, nxy, rnxy, rxy);
                         gj = (int)divmod53(rxy, nx64, rnx, ri);
                         gi = (int)ri;
-                        const int g3[3] = {gi, gj, gk};
-                        const int n3[3] = {fnx, fny, fnz};
-                        const int p3[3] = {fpx, fpy, fpz};
-                        ext = 0;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            if (p3[a] || g3[a] - 1 >= 0) ext |= 1u << a;
-                            if (p3[a] || g3[a] + 2 < n3[a]) ext |= 8u << a;
-                        }
+                        ext = patch_ext(gi, gj, gk, fnx, fny, fnz, fpx, fpy, fpz);
                         ccode = -1;  // force a corner fetch at the first evaluation
                         status = 0;
                         iters = 0;
                         dit = 0;
                         nit = 0;
                         converged = false;
-                        // first estimate: mean of the centres of the pierced faces (-x,+x,-y,+y,-z,+z)
-                        float sx = 0.f, sy = 0.f, sz = 0.f;
-                        int npierced = 0;
-#pragma unroll
-                        for (int fc = 0; fc < 6; ++fc) {
-                            if (dec2(desc, fc) == 0) continue;
-                            const int a = fc >> 1;
-                            const float side = (float)(fc & 1);
-                            sx += a == 0 ? side : 0.5f;
-                            sy += a == 1 ? side : 0.5f;
-                            sz += a == 2 ? side : 0.5f;
-                            ++npierced;
-                        }
-                        if (npierced == 0) {
-                            x0 = v3(0.5f, 0.5f, 0.5f);
-                            status |= VX_SAMPLE_NO_FACES;
-                        } else {
-                            const float inv = 1.0f / (float)npierced;
-                            x0 = v3(sx * inv, sy * inv, sz * inv);
-                        }
-                        if (npierced >= 4) status |= VX_SAMPLE_MULTI;
+                        x0 = first_estimate(desc, status);
                         if (A.seed) x0 = v3(A.seed[3 * s], A.seed[3 * s + 1], A.seed[3 * s + 2]);
                         xt = x0;
                         phase = PH_INIT;
@@ -295,16 +450,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         if (phase != PH_IDLE) {
             int c[3];
             float u[3];
-            const float xs[3] = {xt.x, xt.y, xt.z};
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int lo = (ext >> a) & 1u ? -1 : 0, hi = (ext >> (3 + a)) & 1u ? 1 : 0;
-                int fl = (int)floorf(xs[a]);
-                fl = max(lo, min(fl, hi));
-                c[a] = fl;
-                u[a] = xs[a] - (float)fl;
-            }
-            const int code = (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
+            const int code = locate(xt, ext, c, u);
             if (code != ccode) {
                 ccode = code;
                 const float2 *psi_p = A.psi;
@@ -319,87 +465,20 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                     fpy = (int)((F.periodic >> 1) & 1u);
                     fpz = (int)((F.periodic >> 2) & 1u);
                 }
-                const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
-                const int64_t i0 = wrap((int64_t)gi + c[0], fnx, fpx);
-                const int64_t i1 = wrap((int64_t)gi + c[0] + 1, fnx, fpx);
-                const int64_t j0 = wrap((int64_t)gj + c[1], fny, fpy);
-                const int64_t j1 = wrap((int64_t)gj + c[1] + 1, fny, fpy);
-                const int64_t k0 = wrap((int64_t)gk + c[2], fnz, fpz);
-                const int64_t k1 = wrap((int64_t)gk + c[2] + 1, fnz, fpz);
-                const float2 *r00 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
-                const float2 *r10 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
-                const float2 *r01 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
-                const float2 *r11 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k1;
-                const float2 c0 = r00[i0], c1 = r00[i1], c2 = r10[i0], c3 = r10[i1];
-                const float2 c4 = r01[i0], c5 = r01[i1], c6 = r11[i0], c7 = r11[i1];
-                s_corner[0][tid] = c0;
-                s_corner[1][tid] = c1;
-                s_corner[2][tid] = c2;
-                s_corner[3][tid] = c3;
-                s_corner[4][tid] = c4;
-                s_corner[5][tid] = c5;
-                s_corner[6][tid] = c6;
-                s_corner[7][tid] = c7;
+                float2 w[8];
+                fetch_corners(psi_p, fnx, fny, fnz, fpx, fpy, fpz, gi, gj, gk, c, w);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) s_corner[d][tid] = w[d];
             }
             float2 v[8];
 #pragma unroll
             for (int d = 0; d < 8; ++d) v[d] = s_corner[d][tid];
-            const float ux = u[0], uy = u[1], uz = u[2];
-            const float mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
-            const float2 a00 = make_float2(mx * v[0].x + ux * v[1].x, mx * v[0].y + ux * v[1].y);
-            const float2 a10 = make_float2(mx * v[2].x + ux * v[3].x, mx * v[2].y + ux * v[3].y);
-            const float2 a01 = make_float2(mx * v[4].x + ux * v[5].x, mx * v[4].y + ux * v[5].y);
-            const float2 a11 = make_float2(mx * v[6].x + ux * v[7].x, mx * v[6].y + ux * v[7].y);
-            const float2 d00 = make_float2(v[1].x - v[0].x, v[1].y - v[0].y);
-            const float2 d10 = make_float2(v[3].x - v[2].x, v[3].y - v[2].y);
-            const float2 d01 = make_float2(v[5].x - v[4].x, v[5].y - v[4].y);
-            const float2 d11 = make_float2(v[7].x - v[6].x, v[7].y - v[6].y);
-            const float2 b0 = make_float2(my * a00.x + uy * a10.x, my * a00.y + uy * a10.y);
-            const float2 b1 = make_float2(my * a01.x + uy * a11.x, my * a01.y + uy * a11.y);
-            tr = mz * b0.x + uz * b1.x;
-            ti = mz * b0.y + uz * b1.y;
-            tgr.z = b1.x - b0.x;
-            tgi.z = b1.y - b0.y;
-            const float2 ey0 = make_float2(a10.x - a00.x, a10.y - a00.y);
-            const float2 ey1 = make_float2(a11.x - a01.x, a11.y - a01.y);
-            tgr.y = mz * ey0.x + uz * ey1.x;
-            tgi.y = mz * ey0.y + uz * ey1.y;
-            const float2 ex0 = make_float2(my * d00.x + uy * d10.x, my * d00.y + uy * d10.y);
-            const float2 ex1 = make_float2(my * d01.x + uy * d11.x, my * d01.y + uy * d11.y);
-            tgr.x = mz * ex0.x + uz * ex1.x;
-            tgi.x = mz * ex0.y + uz * ex1.y;
+            trilinear(v, u, tr, ti, tgr, tgi);
         }
 
         // ---- first evaluation of a sample: plane normal to the pseudo-vorticity at x0
         if (phase == PH_INIT) {
-            V3 t = crs(tgr, tgi);
-            float tn = nrm(t);
-            if (!(tn > 1e-6f * nrm(tgr) * nrm(tgi)) || tn == 0.f) {
-                status |= VX_SAMPLE_TANGENT_FALLBACK;
-                t = v3((float)(dec2(desc, 0) + dec2(desc, 1)), (float)(dec2(desc, 2) + dec2(desc, 3)),
-                       (float)(dec2(desc, 4) + dec2(desc, 5)));
-                if (nrm(t) == 0.f) {
-                    t = v3(0.f, 0.f, 1.f);
-                    for (int fc = 0; fc < 6; ++fc) {
-                        const int w = dec2(desc, fc);
-                        if (w != 0) {
-                            const int a = fc >> 1;
-                            t = v3(a == 0 ? (float)w : 0.f, a == 1 ? (float)w : 0.f, a == 2 ? (float)w : 0.f);
-                            break;
-                        }
-                    }
-                }
-                tn = nrm(t);
-            }
-            const float itn = rcp(tn);
-            t = v3(t.x * itn, t.y * itn, t.z * itn);
-            int ax = 0;
-            if (fabsf(t.y) < fabsf(comp(t, ax))) ax = 1;
-            if (fabsf(t.z) < fabsf(comp(t, ax))) ax = 2;
-            e1 = crs(t, v3(ax == 0 ? 1.f : 0.f, ax == 1 ? 1.f : 0.f, ax == 2 ? 1.f : 0.f));
-            const float in1 = rsq(dot(e1, e1));
-            e1 = v3(e1.x * in1, e1.y * in1, e1.z * in1);
-            e2 = crs(t, e1);
+            plane_basis(tgr, tgi, desc, e1, e2, status);
             ty1 = 0.f;  // taken over as the current point below
             ty2 = 0.f;
             s_prev = 0.5f * P.step0;
@@ -447,16 +526,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             bool ok = false;
             if (mode == MODE_DESCENT) {
                 if (dit < P.max_descent && f != 0.f) {
-                    const V3 G = v3(2.f * (vr * gr.x + vi * gim.x), 2.f * (vr * gr.y + vi * gim.y),
-                                    2.f * (vr * gr.z + vi * gim.z));
-                    const float g1 = dot(e1, G), g2 = dot(e2, G);
-                    const float gg = g1 * g1 + g2 * g2;
-                    const float ig = rsq(gg);
-                    gn = gg * ig;
-                    ok = gg > 0.f && ig < INFINITY;
-                    n1 = -g1;
-                    n2 = -g2;
-                    den = ig;  // direction = -g / |g|
+                    ok = descent_dir(vr, vi, gr, gim, e1, e2, n1, n2, den, gn);
                     alpha = fminf(2.f * s_prev, P.step_max);
                 }
                 if (!ok) {
@@ -468,14 +538,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                     if (f == 0.f) {
                         converged = true;
                     } else {
-                        const float j00 = dot(e1, gr), j01 = dot(e2, gr);
-                        const float j10 = dot(e1, gim), j11 = dot(e2, gim);
-                        const float det = j00 * j11 - j01 * j10;
-                        const float idet = rcp(det);
-                        ok = det != 0.f && fabsf(idet) < INFINITY;
-                        n1 = -(j11 * vr - j01 * vi);
-                        n2 = -(-j10 * vr + j00 * vi);
-                        den = idet;
+                        ok = newton_dir(vr, vi, gr, gim, e1, e2, n1, n2, den);
                         alpha = 1.f;
                     }
                 }
@@ -494,12 +557,8 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             while (hv < P.max_halvings) {
                 ty1 = y1 + alpha * p1;
                 ty2 = y2 + alpha * p2;
-                xt = v3(x0.x + ty1 * e1.x + ty2 * e2.x, x0.y + ty1 * e1.y + ty2 * e2.y,
-                        x0.z + ty1 * e1.z + ty2 * e2.z);
-                const float lx = (ext & 1u) ? -1.f : 0.f, ly = (ext & 2u) ? -1.f : 0.f;
-                const float lz = (ext & 4u) ? -1.f : 0.f, hx = (ext & 8u) ? 2.f : 1.f;
-                const float hy = (ext & 16u) ? 2.f : 1.f, hz = (ext & 32u) ? 2.f : 1.f;
-                if (xt.x >= lx && xt.x <= hx && xt.y >= ly && xt.y <= hy && xt.z >= lz && xt.z <= hz) {
+                xt = plane_point(x0, e1, e2, ty1, ty2);
+                if (in_patch(xt, ext)) {
                     // a Newton trial point equal to the current point (as is then every shorter
                     // one) is rejected at this and every remaining halving: |psi|^2 cannot decrease
                     if (mode == MODE_NEWTON && ty1 == y1 && ty2 == y2) stuck = true;
@@ -525,9 +584,10 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             // the current point, computed exactly as when it was a trial point
             vx_sample o;
             o.cell = cell;
-            o.off[0] = x0.x + y1 * e1.x + y2 * e2.x;
-            o.off[1] = x0.y + y1 * e1.y + y2 * e2.y;
-            o.off[2] = x0.z + y1 * e1.z + y2 * e2.z;
+            const V3 xe = plane_point(x0, e1, e2, y1, y2);
+            o.off[0] = xe.x;
+            o.off[1] = xe.y;
+            o.off[2] = xe.z;
             o.rho = f;
             o.iters = (uint16_t)min(iters, 65535);
             o.status = (uint16_t)status;
@@ -535,6 +595,188 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             if constexpr (BATCH) s_fr[fr].out[s] = o;
             else A.out[A.out_index ? A.out_index[s] : s] = o;
             phase = PH_IDLE;
+        }
+    }
+}
+
+// Short lists. A list that does not fill the chip (the fallback cells of the surrogate, say) takes
+// as long as its slowest sample, and refine_k spends one pass per evaluation: a slowly converging
+// descent pays two or three passes per accepted step (the trial at twice the last length, rejected,
+// then the halved one). Here a group of SPEC_G lanes runs one sample and evaluates the trial points
+// of SPEC_G consecutive halvings of the current step at once (lane h: the length halved h more
+// times). The first of them at which the sequential rule stops (accepted, or a Newton step that no
+// longer moves the point) decides, and its values are broadcast from its lane, so that a step costs
+// one pass; the points outside the patch before it set VX_SAMPLE_BOUNDARY as they would have one at
+// a time. Every lane of a group holds the sample's state. The arithmetic is refine_k's: the shared
+// functions above, the same expressions for the trial point and the acceptance tests, and halvings
+// as the same sequence of exact multiplications by 1/2, so the samples are bit-identical to refine_k's.
+// A lane keeps the corners of the cell of its last evaluation in registers.
+constexpr int SPEC_G = 16;
+
+__device__ __forceinline__ float halve_n(float a, int n) {  // n multiplications by 0.5f, n in [0, SPEC_G]
+#pragma unroll
+    for (int j = 0; j < SPEC_G; ++j) a = j < n ? 0.5f * a : a;
+    return a;
+}
+
+__global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t run_limit) {
+    const int tid = threadIdx.x, lane = tid & 63, h = lane & (SPEC_G - 1), gl = lane - h;
+    if (blockIdx.x == 0 && tid == 0) *A.chunks = 0ull;  // chunk counter of the refine_k launch that follows
+    const int64_t n = min(*A.count, A.cap);
+    if (n > run_limit) return;  // a long list, refined by refine_k (uniform)
+    const vx_refine_params &P = A.p;
+    const int64_t ngroups = (int64_t)gridDim.x * (REF_THREADS / SPEC_G);
+    const uint64_t nx64 = (uint64_t)A.nx, nxy = nx64 * (uint64_t)A.ny;
+    const double rnx = 1.0 / (double)A.nx, rnxy = 1.0 / ((double)A.nx * (double)A.ny);
+    for (int64_t s = (int64_t)blockIdx.x * (REF_THREADS / SPEC_G) + tid / SPEC_G; s < n; s += ngroups) {
+        const uint64_t cell = A.cells[s];
+        const uint32_t desc = A.desc[s];
+        vx_sample *dst = A.out + (A.out_index ? A.out_index[s] : s);
+        if (cell >= nxy * (uint64_t)A.nz) {
+            if (h == 0) {
+                vx_sample o{};
+                o.cell = cell;
+                o.rho = -1.f;
+                o.status = (uint16_t)VX_SAMPLE_BAD_CELL;
+                *dst = o;
+            }
+            continue;
+        }
+        uint64_t rxy, ri;
+        const int gk = (int)divmod53(cell, nxy, rnxy, rxy);
+        const int gj = (int)divmod53(rxy, nx64, rnx, ri);
+        const int gi = (int)ri;
+        const uint32_t ext = patch_ext(gi, gj, gk, A.nx, A.ny, A.nz, A.px, A.py, A.pz);
+        uint32_t status = 0;
+        V3 x0 = first_estimate(desc, status);
+        if (A.seed) x0 = v3(A.seed[3 * s], A.seed[3 * s + 1], A.seed[3 * s + 2]);
+        int ccode = -1;
+        float2 cw[8];
+        auto eval = [&](const V3 &xt, float &tr, float &ti, V3 &tgr, V3 &tgi) {
+            int c[3];
+            float u[3];
+            const int code = locate(xt, ext, c, u);
+            if (code != ccode) {
+                ccode = code;
+                fetch_corners(A.psi, A.nx, A.ny, A.nz, A.px, A.py, A.pz, gi, gj, gk, c, cw);
+            }
+            trilinear(cw, u, tr, ti, tgr, tgi);
+        };
+        // first evaluation, at x0 (every lane of the group), and the plane of the search
+        float tr, ti;
+        V3 tgr, tgi, e1, e2;
+        eval(x0, tr, ti, tgr, tgi);
+        plane_basis(tgr, tgi, desc, e1, e2, status);
+        float y1 = 0.f, y2 = 0.f, vr = tr, vi = ti;
+        V3 gr = tgr, gim = tgi;
+        float f = tr * tr + ti * ti;
+        float s_prev = 0.5f * P.step0, gn = 0.f;
+        float alpha = 0.f, p1 = 0.f, p2 = 0.f;  // current step: length at halving hv, direction
+        int mode = MODE_DESCENT, dit = 0, nit = 0, hv = 0, iters = 0;
+        bool converged = false, done = false;
+        // start a step of the current kind (a descent that cannot start hands over to Newton at
+        // once), or end the sample
+        auto begin = [&]() {
+            float n1 = 0.f, n2 = 0.f, den = 1.f;
+            bool ok = false;
+            if (mode == MODE_DESCENT) {
+                if (dit < P.max_descent && f != 0.f) {
+                    ok = descent_dir(vr, vi, gr, gim, e1, e2, n1, n2, den, gn);
+                    alpha = fminf(2.f * s_prev, P.step_max);
+                }
+                if (!ok) mode = MODE_NEWTON;
+            }
+            if (mode == MODE_NEWTON) {
+                if (nit < P.max_newton) {
+                    if (f == 0.f) {
+                        converged = true;
+                    } else {
+                        ok = newton_dir(vr, vi, gr, gim, e1, e2, n1, n2, den);
+                        alpha = 1.f;
+                    }
+                }
+                if (!ok) done = true;
+            }
+            if (ok) {
+                p1 = n1 * den;
+                p2 = n2 * den;
+                hv = 0;
+            }
+        };
+        begin();
+        while (!done) {
+            const float a = halve_n(alpha, h);
+            const float ty1 = y1 + a * p1;
+            const float ty2 = y2 + a * p2;
+            const V3 xt = plane_point(x0, e1, e2, ty1, ty2);
+            const bool valid = hv + h < P.max_halvings;
+            const bool inside = valid && in_patch(xt, ext);
+            const bool stuck = inside && mode == MODE_NEWTON && ty1 == y1 && ty2 == y2;
+            tr = 0.f;
+            ti = 0.f;
+            tgr = v3(0.f, 0.f, 0.f);
+            tgi = tgr;
+            if (inside && !stuck) eval(xt, tr, ti, tgr, tgi);
+            const float ft = tr * tr + ti * ti;
+            const bool descent = mode == MODE_DESCENT;
+            const bool acc = inside && !stuck && (descent ? (ft <= f - P.armijo * a * gn) : (ft < f));
+            const uint32_t res = (uint32_t)(__ballot(stuck || acc) >> gl) & ((1u << SPEC_G) - 1u);
+            const uint32_t outside = (uint32_t)(__ballot(valid && !inside) >> gl) & ((1u << SPEC_G) - 1u);
+            if (res) {
+                const int hs = __builtin_ctz(res), src = gl + hs;
+                if (outside & ((1u << hs) - 1u)) status |= VX_SAMPLE_BOUNDARY;
+                if (__shfl((int)stuck, src)) {
+                    done = true;
+                } else {
+                    const float aa = __shfl(a, src);
+                    y1 = __shfl(ty1, src);
+                    y2 = __shfl(ty2, src);
+                    vr = __shfl(tr, src);
+                    vi = __shfl(ti, src);
+                    gr = v3(__shfl(tgr.x, src), __shfl(tgr.y, src), __shfl(tgr.z, src));
+                    gim = v3(__shfl(tgi.x, src), __shfl(tgi.y, src), __shfl(tgi.z, src));
+                    f = __shfl(ft, src);
+                    ++iters;
+                    if (descent) {
+                        ++dit;
+                        s_prev = aa;
+                    } else {
+                        ++nit;
+                    }
+                    const bool conv_now = !descent && aa * sqrtf(p1 * p1 + p2 * p2) < P.newton_tol;
+                    converged = converged || conv_now;
+                    if (descent && aa < P.descent_tol) mode = MODE_NEWTON;
+                    if (conv_now) done = true;
+                    else begin();
+                }
+            } else {
+                if (outside) status |= VX_SAMPLE_BOUNDARY;
+                hv += SPEC_G;
+                alpha = halve_n(alpha, SPEC_G);
+                if (hv >= P.max_halvings) {
+                    if (mode == MODE_DESCENT) {
+                        mode = MODE_NEWTON;
+                        begin();
+                    } else {
+                        done = true;
+                    }
+                }
+            }
+        }
+        if (h == 0) {
+            if (f > P.rho_tol) status |= VX_SAMPLE_NONZERO_MIN;
+            if (!converged && f > P.rho_tol) status |= VX_SAMPLE_NOT_CONVERGED;
+            vx_sample o;
+            o.cell = cell;
+            const V3 xe = plane_point(x0, e1, e2, y1, y2);
+            o.off[0] = xe.x;
+            o.off[1] = xe.y;
+            o.off[2] = xe.z;
+            o.rho = f;
+            o.iters = (uint16_t)min(iters, 65535);
+            o.status = (uint16_t)status;
+            o.reserved = 0;
+            *dst = o;
         }
     }
 }
@@ -556,6 +798,20 @@ int64_t ref_blocks(vx_handle *h, K kernel, int &per_cu, int64_t cap) {
     const int64_t resident = (int64_t)per_cu * (h->num_cu > 0 ? h->num_cu : 256);
     const int64_t need = (cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);  // >= one chunk per wavefront
     return std::max<int64_t>(1, std::min(need, resident));
+}
+
+// resident workgroups of refine_spec_k; -1 on error
+int64_t spec_blocks(vx_handle *h) {
+    if (h->refs_blocks_per_cu <= 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, refine_spec_k, REF_THREADS, 0);
+        if (e != hipSuccess) {
+            vx_hip_check(h, e, "refine_spec_k occupancy");
+            return -1;
+        }
+        h->refs_blocks_per_cu = nb > 0 ? nb : 1;
+    }
+    return (int64_t)h->refs_blocks_per_cu * (h->num_cu > 0 ? h->num_cu : 256);
 }
 
 }  // namespace
@@ -581,13 +837,23 @@ vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, cons
     A.pz = (int)((d.periodic >> 2) & 1u);
     A.p = p;
     const int64_t blocks = ref_blocks(h, refine_k<false>, h->ref_blocks_per_cu, cap);
-    if (blocks < 0) return VX_ERR_DEVICE;
+    const int64_t sblocks = spec_blocks(h);
+    if (blocks < 0 || sblocks < 0) return VX_ERR_DEVICE;
+    // the number of samples is known on the device only: refine_spec_k takes lists of at most one
+    // sample per resident group and zeroes the chunk counter, refine_k (if the capacity allows a
+    // longer list) the others; each returns at once when the list is not its own
+    constexpr int64_t GPB = REF_THREADS / SPEC_G;  // groups per workgroup
+    const int64_t limit = sblocks * GPB;
+    const bool short_only = cap <= limit;
+    const int64_t sgrid = std::max<int64_t>(1, std::min(sblocks, (cap + GPB - 1) / GPB));
     vx_timer tm(h, s, VX_KIND_REFINE);
-    hipLaunchKernelGGL(zero_u64_k, dim3(1), dim3(1), 0, s, h->d_work);
-    hipLaunchKernelGGL(refine_k<false>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A,
-                       (const vx_ref_frame *)nullptr, 1, h->ref_refill);
+    hipLaunchKernelGGL(refine_spec_k, dim3((unsigned)sgrid), dim3(REF_THREADS), 0, s, A,
+                       short_only ? INT64_MAX : limit);
+    if (!short_only)
+        hipLaunchKernelGGL(refine_k<false>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A,
+                           (const vx_ref_frame *)nullptr, 1, h->ref_refill, limit);
     tm.stop();
-    return vx_hip_check(h, hipGetLastError(), "refine_k launch");
+    return vx_hip_check(h, hipGetLastError(), "refine launch");
 }
 
 vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
@@ -601,6 +867,6 @@ vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, in
     if (blocks < 0) return VX_ERR_DEVICE;
     hipLaunchKernelGGL(zero_u64_k, dim3(1), dim3(1), 0, s, d_counter);
     hipLaunchKernelGGL(refine_k<true>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A, d_frames, nframes,
-                       h->ref_refill);
+                       h->ref_refill, (int64_t)-1);
     return vx_hip_check(h, hipGetLastError(), "refine_k batch launch");
 }

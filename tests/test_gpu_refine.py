@@ -138,3 +138,55 @@ def test_refine_seeds_and_bad_cells(ex):
     keep = np.setdiff1d(np.arange(nc), pos)
     for k in ("off", "rho", "iters", "status"):
         assert np.array_equal(mixed[k][keep], base[k][keep]), k
+
+
+@pytest.mark.parametrize("periodic", [7, 0])
+def test_short_list_bit_identical(ex, periodic):
+    """A list short enough for the short-list kernel (one sample per group of lanes, the halvings of a
+    step evaluated together) gives the samples of the long-list kernel bit for bit: the 512^3 tangle's
+    full list (half a million cells) against subsets of it: random cells, the slowest ones, with
+    out-of-range ids mixed in, and the empty list."""
+    import torch
+    from paper_1911_12070_amd import SAMPLE_BAD_CELL, samples_to_numpy
+    psi = ex.gen_tangle(vxinputs.tangle_512())
+    nz, ny, nx = psi.shape
+    out = ex.alloc_winding(psi.shape, face_cap=nx * ny * nz // 16, cell_cap=nx * ny * nz // 16, wind=False)
+    ex.winding(psi, periodic, out)
+    torch.cuda.synchronize()
+    nc = int(out["counts"][1].cpu())
+    assert nc > 200_000
+    full = samples_to_numpy(ex.refine(psi, out, periodic), nc)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    slow = np.argsort(-full["iters"].astype(np.int64), kind="stable")[:1000]
+    subsets = {"random": np.sort(rng.choice(nc, 5000, replace=False)), "slowest": slow,
+               "one": np.array([int(slow[0])])}
+    for name, idx in subsets.items():
+        sel = torch.from_numpy(idx.astype(np.int64)).cuda()
+        sub = {"cells": out["cells"][sel].contiguous(), "cdesc": out["cdesc"][sel].contiguous(),
+               "counts": torch.tensor([0, len(idx)], dtype=torch.int64, device="cuda")}
+        got = samples_to_numpy(ex.refine(psi, sub, periodic), len(idx))
+        torch.cuda.synchronize()
+        log(f"periodic={periodic} {name}: {len(idx)} samples, iters max {int(got['iters'].max())}, "
+            f"boundary {int(((got['status'] & oracle.BOUNDARY) != 0).sum())}")
+        assert got.tobytes() == full[idx].tobytes(), name
+    # out-of-range ids inside a short list
+    idx = subsets["random"][:300]
+    cells = out["cells"][torch.from_numpy(idx.astype(np.int64)).cuda()].clone()
+    bad_pos = [0, 150, 299]
+    for p, b in zip(bad_pos, [nx * ny * nz, nx * ny * nz + 7, -1]):
+        cells[p] = b
+    sub = {"cells": cells, "cdesc": out["cdesc"][torch.from_numpy(idx.astype(np.int64)).cuda()].contiguous(),
+           "counts": torch.tensor([0, len(idx)], dtype=torch.int64, device="cuda")}
+    got = samples_to_numpy(ex.refine(psi, sub, periodic), len(idx))
+    torch.cuda.synchronize()
+    keep = np.setdiff1d(np.arange(len(idx)), bad_pos)
+    assert got[keep].tobytes() == full[idx[keep]].tobytes()
+    assert all(got["status"][p] == SAMPLE_BAD_CELL and got["rho"][p] == -1.0 for p in bad_pos)
+    # an empty list writes nothing
+    sub["counts"] = torch.zeros(2, dtype=torch.int64, device="cuda")
+    marker = ex.alloc_samples(4)
+    marker.fill_(7)
+    ex.refine(psi, sub, periodic, marker)
+    torch.cuda.synchronize()
+    assert bool((marker == 7).all())
