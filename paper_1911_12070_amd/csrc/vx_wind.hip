@@ -114,6 +114,33 @@ __device__ __forceinline__ uint32_t piece_off(int r, int q) {
     return (uint32_t)(r * 1024 + (cc * 16 + ((q + r + 4 * cc) & 15)) * 16);
 }
 
+// 4x4 byte transpose: t[j] = byte j of w0, w1, w2, w3 (in bytes 0..3), eight v_perm_b32
+__device__ __forceinline__ void byte_transpose4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t t[4]) {
+    const uint32_t a0 = __builtin_amdgcn_perm(w1, w0, 0x06020400u), a1 = __builtin_amdgcn_perm(w1, w0, 0x07030501u);
+    const uint32_t a2 = __builtin_amdgcn_perm(w3, w2, 0x06020400u), a3 = __builtin_amdgcn_perm(w3, w2, 0x07030501u);
+    t[0] = __builtin_amdgcn_perm(a2, a0, 0x05040100u);
+    t[1] = __builtin_amdgcn_perm(a3, a1, 0x05040100u);
+    t[2] = __builtin_amdgcn_perm(a2, a0, 0x07060302u);
+    t[3] = __builtin_amdgcn_perm(a3, a1, 0x07060302u);
+}
+
+// transpose of the 8x8 bit matrix held in (lo, hi) with row r in byte r and column c in bit c of
+// that byte: three exchange rounds (bit pairs, 2x2 blocks, 4x4 blocks)
+__device__ __forceinline__ void bit_transpose8(uint32_t &lo, uint32_t &hi) {
+    uint32_t t0, t1;
+    t0 = (lo ^ ((lo >> 7) | (hi << 25))) & 0x00AA00AAu;
+    t1 = (hi ^ (hi >> 7)) & 0x00AA00AAu;
+    lo ^= t0 ^ (t0 << 7);
+    hi ^= t1 ^ ((t1 << 7) | (t0 >> 25));
+    t0 = (lo ^ ((lo >> 14) | (hi << 18))) & 0x0000CCCCu;
+    t1 = (hi ^ (hi >> 14)) & 0x0000CCCCu;
+    lo ^= t0 ^ (t0 << 14);
+    hi ^= t1 ^ ((t1 << 14) | (t0 >> 18));
+    t0 = (lo ^ (hi << 4)) & 0xF0F0F0F0u;
+    lo ^= t0;
+    hi ^= t0 >> 4;
+}
+
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void wait_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
@@ -152,6 +179,7 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
     // interior tiles use 16-byte loads of whole rows; others (ragged last column tile, odd nx) load
     // per node
     const bool fast = A.psi_a16 && (x0 + TXO <= nx) && ((nx & 1) == 0);
+    const bool yin = y0 + 16 <= ny;
 
     const float2 *psi = A.psi;
     const uint64_t plane_nodes = (uint64_t)nx * (uint64_t)ny;
@@ -167,14 +195,20 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
         const float2 *pl = psi + (uint64_t)plane_of(k) * plane_nodes;
         if (fast) {
             const int cc = lane >> 4, xx = lane & 15;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                // row j: lane L lands at slot L; it fetches the piece whose rotated slot is L
+            // row j: lane L lands at slot L; it fetches the piece whose rotated slot is L
+            auto row_load = [&](int j, const float2 *row) {
                 const int q = 16 * cc + ((xx - j - 4 * cc) & 15);
-                const float2 *src = pl + (uint64_t)row_of(j) * nx + x0 + 2 * q;
-                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(row + 2 * q),
                                                  (void __attribute__((address_space(3))) *)(s_plane + j * 1024),
                                                  16, 0, 0);
+            };
+            if (yin) {  // rows y0 .. y0+15 of the grid: one pointer stepped by a row (uniform branch)
+                const float2 *row = pl + (uint64_t)y0 * nx + x0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j, row += nx) row_load(j, row);
+            } else {  // the tile reaches past the last grid row: wrapped or clamped rows
+#pragma unroll
+                for (int j = 0; j < 16; ++j) row_load(j, pl + (uint64_t)row_of(j) * nx + x0);
             }
         } else {
             const float2 *rowp = pl + (uint64_t)yl * nx;
@@ -402,17 +436,16 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
         // packed bytes of this row: bit0 w_x != 0, bit1 w_x < 0, bit2/3 w_y, bit4/5 w_z, bit6 cell.
         // They are written at the start of the next step, before that step's prefetch, so that the
         // wait for the prefetch never waits on these stores.
+        // (bit b of node i's byte is bit i of word b: per 8 nodes an 8x8 bit transpose)
         if (A.wind) {
-            const uint32_t wrd[7] = {nzx, wx.n, nzy, wy.n, nz0, wz0.n, pc};
+            uint32_t lo[4], hi[4];
+            byte_transpose4(nzx, wx.n, nzy, wy.n, lo);
+            byte_transpose4(nz0, wz0.n, pc, 0u, hi);
 #pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int b = 0; b < 7; ++b) {
-                    const uint32_t nib = (wrd[b] >> (4 * g)) & 0xfu;
-                    v |= (__umul24(nib, 0x204081u) & 0x01010101u) << b;
-                }
-                pend[g] = v;
+            for (int j = 0; j < 4; ++j) {
+                bit_transpose8(lo[j], hi[j]);
+                pend[2 * j] = lo[j];
+                pend[2 * j + 1] = hi[j];
             }
             pend_k = k;
         }
