@@ -206,8 +206,9 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
                 const float2 *row = pl + (uint64_t)y0 * nx + x0;
 #pragma unroll
                 for (int j = 0; j < 16; ++j, row += nx) row_load(j, row);
-            } else {  // the tile reaches past the last grid row: wrapped or clamped rows
-#pragma unroll
+            } else {  // the tile reaches past the last grid row: wrapped or clamped rows (a loop, so
+                      // that no row pointer stays live across the march)
+#pragma unroll 1
                 for (int j = 0; j < 16; ++j) row_load(j, pl + (uint64_t)row_of(j) * nx + x0);
             }
         } else {
@@ -331,14 +332,14 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
             if (faces) {
                 const uint64_t e = s_fbuf[i];
                 if (idx < A.fcap) {
-                    A.faces[idx] = e >> 1;
-                    A.fsign[idx] = (e & 1) ? (int8_t)-1 : (int8_t)1;
+                    __builtin_nontemporal_store(e >> 1, A.faces + idx);
+                    __builtin_nontemporal_store((e & 1) ? (int8_t)-1 : (int8_t)1, A.fsign + idx);
                 }
             } else {
                 const uint64_t e = s_cbuf[i];
                 if (idx < A.ccap) {
-                    A.cells[idx] = e >> 12;
-                    A.cdesc[idx] = (uint16_t)(e & 0xfffu);
+                    __builtin_nontemporal_store(e >> 12, A.cells + idx);
+                    __builtin_nontemporal_store((uint16_t)(e & 0xfffu), A.cdesc + idx);
                 }
             }
         }
@@ -363,8 +364,10 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
         if (pend_k < 0 || !row_out || ncol == 0) return;
         uint8_t *dst = A.wind + (uint64_t)pend_k * plane_nodes + (uint64_t)yg * nx + xl0;
         if (ncol == 32 && (nx & 15) == 0 && A.wind_a16) {
-            reinterpret_cast<uint4 *>(dst)[0] = make_uint4(pend[0], pend[1], pend[2], pend[3]);
-            reinterpret_cast<uint4 *>(dst)[1] = make_uint4(pend[4], pend[5], pend[6], pend[7]);
+            // streaming stores: the field is not read again by this kernel
+            typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store((u4v){pend[0], pend[1], pend[2], pend[3]}, reinterpret_cast<u4v *>(dst));
+            __builtin_nontemporal_store((u4v){pend[4], pend[5], pend[6], pend[7]}, reinterpret_cast<u4v *>(dst) + 1);
         } else if (ncol == 32 && (nx & 3) == 0 && A.wind_a4) {
 #pragma unroll
             for (int g = 0; g < 8; ++g) reinterpret_cast<uint32_t *>(dst)[g] = pend[g];
