@@ -332,14 +332,14 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
             if (faces) {
                 const uint64_t e = s_fbuf[i];
                 if (idx < A.fcap) {
-                    __builtin_nontemporal_store(e >> 1, A.faces + idx);
-                    __builtin_nontemporal_store((e & 1) ? (int8_t)-1 : (int8_t)1, A.fsign + idx);
+                    A.faces[idx] = e >> 1;
+                    A.fsign[idx] = (e & 1) ? (int8_t)-1 : (int8_t)1;
                 }
             } else {
                 const uint64_t e = s_cbuf[i];
                 if (idx < A.ccap) {
-                    __builtin_nontemporal_store(e >> 12, A.cells + idx);
-                    __builtin_nontemporal_store((uint16_t)(e & 0xfffu), A.cdesc + idx);
+                    A.cells[idx] = e >> 12;
+                    A.cdesc[idx] = (uint16_t)(e & 0xfffu);
                 }
             }
         }
