@@ -45,7 +45,6 @@ __device__ __forceinline__ float dot(const V3 &a, const V3 &b) { return a.x * b.
 __device__ __forceinline__ V3 crs(const V3 &a, const V3 &b) {
     return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
-__device__ __forceinline__ float nrm(const V3 &a) { return sqrtf(dot(a, a)); }
 // hardware reciprocal square root and reciprocal (about 1 ulp): the normalisations and step
 // directions they feed are search directions, whose last-bit rounding does not move the minimum
 __device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
@@ -159,33 +158,44 @@ __device__ __forceinline__ void fetch_corners(const float2 *psi_p, int fnx, int 
     v[7] = r11[i1];
 }
 
-// trilinear psi and its gradient (cell units) at local coordinates u of a cell with corners v
-__device__ __forceinline__ void trilinear(const float2 v[8], const float u[3], float &tr, float &ti, V3 &tgr,
+// The trilinear interpolant of a cell as a polynomial in the local coordinates (u, v, w):
+// f = c0 + c1 u + c2 v + c3 w + c4 uv + c5 uw + c6 vw + c7 uvw, from the corners d = dx + 2 dy + 4 dz
+// (computed once per cell change, then cached)
+__device__ __forceinline__ void tri_coeffs(const float2 v[8], float2 c[8]) {
+    auto sub = [](float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); };
+    c[0] = v[0];
+    c[1] = sub(v[1], v[0]);
+    c[2] = sub(v[2], v[0]);
+    c[3] = sub(v[4], v[0]);
+    const float2 d32 = sub(v[3], v[2]), d54 = sub(v[5], v[4]), d64 = sub(v[6], v[4]), d76 = sub(v[7], v[6]);
+    c[4] = sub(d32, c[1]);
+    c[5] = sub(d54, c[1]);
+    c[6] = sub(d64, c[2]);
+    c[7] = sub(sub(d76, d54), c[4]);
+}
+
+// trilinear psi and its gradient (cell units) at local coordinates u of a cell with coefficients c
+// (nested: 11 multiply-adds per component)
+__device__ __forceinline__ void trilinear(const float2 c[8], const float u[3], float &tr, float &ti, V3 &tgr,
                                           V3 &tgi) {
-    const float ux = u[0], uy = u[1], uz = u[2];
-    const float mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
-    const float2 a00 = make_float2(mx * v[0].x + ux * v[1].x, mx * v[0].y + ux * v[1].y);
-    const float2 a10 = make_float2(mx * v[2].x + ux * v[3].x, mx * v[2].y + ux * v[3].y);
-    const float2 a01 = make_float2(mx * v[4].x + ux * v[5].x, mx * v[4].y + ux * v[5].y);
-    const float2 a11 = make_float2(mx * v[6].x + ux * v[7].x, mx * v[6].y + ux * v[7].y);
-    const float2 d00 = make_float2(v[1].x - v[0].x, v[1].y - v[0].y);
-    const float2 d10 = make_float2(v[3].x - v[2].x, v[3].y - v[2].y);
-    const float2 d01 = make_float2(v[5].x - v[4].x, v[5].y - v[4].y);
-    const float2 d11 = make_float2(v[7].x - v[6].x, v[7].y - v[6].y);
-    const float2 b0 = make_float2(my * a00.x + uy * a10.x, my * a00.y + uy * a10.y);
-    const float2 b1 = make_float2(my * a01.x + uy * a11.x, my * a01.y + uy * a11.y);
-    tr = mz * b0.x + uz * b1.x;
-    ti = mz * b0.y + uz * b1.y;
-    tgr.z = b1.x - b0.x;
-    tgi.z = b1.y - b0.y;
-    const float2 ey0 = make_float2(a10.x - a00.x, a10.y - a00.y);
-    const float2 ey1 = make_float2(a11.x - a01.x, a11.y - a01.y);
-    tgr.y = mz * ey0.x + uz * ey1.x;
-    tgi.y = mz * ey0.y + uz * ey1.y;
-    const float2 ex0 = make_float2(my * d00.x + uy * d10.x, my * d00.y + uy * d10.y);
-    const float2 ex1 = make_float2(my * d01.x + uy * d11.x, my * d01.y + uy * d11.y);
-    tgr.x = mz * ex0.x + uz * ex1.x;
-    tgi.x = mz * ex0.y + uz * ex1.y;
+    const float x = u[0], y = u[1], z = u[2];
+    float r[2], gx[2], gy[2], gz[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float c0 = k ? c[0].y : c[0].x, c1 = k ? c[1].y : c[1].x, c2 = k ? c[2].y : c[2].x;
+        const float c3 = k ? c[3].y : c[3].x, c4 = k ? c[4].y : c[4].x, c5 = k ? c[5].y : c[5].x;
+        const float c6 = k ? c[6].y : c[6].x, c7 = k ? c[7].y : c[7].x;
+        const float A = fmaf(c7, z, c4), B = fmaf(c5, z, c1), C = fmaf(c6, z, c2), D = fmaf(c3, z, c0);
+        const float E = fmaf(x, A, C);  // d/dy
+        r[k] = fmaf(y, E, fmaf(x, B, D));
+        gx[k] = fmaf(y, A, B);
+        gy[k] = E;
+        gz[k] = fmaf(x, fmaf(c7, y, c5), fmaf(c6, y, c3));
+    }
+    tr = r[0];
+    ti = r[1];
+    tgr = v3(gx[0], gy[0], gz[0]);
+    tgi = v3(gx[1], gy[1], gz[1]);
 }
 
 // orthonormal basis (e1, e2) of the plane normal to the pseudo-vorticity Re grad psi x Im grad psi
@@ -193,12 +203,13 @@ __device__ __forceinline__ void trilinear(const float2 v[8], const float u[3], f
 __device__ __forceinline__ void plane_basis(const V3 &tgr, const V3 &tgi, uint32_t desc, V3 &e1, V3 &e2,
                                             uint32_t &status) {
     V3 t = crs(tgr, tgi);
-    float tn = nrm(t);
-    if (!(tn > 1e-6f * nrm(tgr) * nrm(tgi)) || tn == 0.f) {
+    // |t| > 1e-6 |grad Re| |grad Im|, compared squared
+    float tt = dot(t, t);
+    if (!(tt > 1e-12f * dot(tgr, tgr) * dot(tgi, tgi)) || tt == 0.f) {
         status |= VX_SAMPLE_TANGENT_FALLBACK;
         t = v3((float)(dec2(desc, 0) + dec2(desc, 1)), (float)(dec2(desc, 2) + dec2(desc, 3)),
                (float)(dec2(desc, 4) + dec2(desc, 5)));
-        if (nrm(t) == 0.f) {
+        if (dot(t, t) == 0.f) {
             t = v3(0.f, 0.f, 1.f);
             for (int fc = 0; fc < 6; ++fc) {
                 const int w = dec2(desc, fc);
@@ -209,9 +220,9 @@ __device__ __forceinline__ void plane_basis(const V3 &tgr, const V3 &tgi, uint32
                 }
             }
         }
-        tn = nrm(t);
+        tt = dot(t, t);
     }
-    const float itn = rcp(tn);
+    const float itn = rsq(tt);
     t = v3(t.x * itn, t.y * itn, t.z * itn);
     int ax = 0;
     if (fabsf(t.y) < fabsf(comp(t, ax))) ax = 1;
@@ -276,7 +287,7 @@ constexpr int MODE_NEWTON = 1;   // Newton on (Re psi, Im psi), halving until |p
 template <bool BATCH>
 __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_frame *frames, int nframes,
                                                         int refill_min, int64_t skip_upto) {
-    // corner cache: corner d (index dx + 2 dy + 4 dz) of the cell cached by thread t at [d][t]
+    // cell cache: interpolation coefficient d of the cell cached by thread t at [d][t]
     __shared__ float2 s_corner[8][REF_THREADS];
     constexpr int NF = BATCH ? VX_BATCH_MAX_FRAMES : 1;
     __shared__ vx_ref_frame s_fr[NF];
@@ -465,10 +476,11 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                     fpy = (int)((F.periodic >> 1) & 1u);
                     fpz = (int)((F.periodic >> 2) & 1u);
                 }
-                float2 w[8];
+                float2 w[8], cf[8];
                 fetch_corners(psi_p, fnx, fny, fnz, fpx, fpy, fpz, gi, gj, gk, c, w);
+                tri_coeffs(w, cf);
 #pragma unroll
-                for (int d = 0; d < 8; ++d) s_corner[d][tid] = w[d];
+                for (int d = 0; d < 8; ++d) s_corner[d][tid] = cf[d];
             }
             float2 v[8];
 #pragma unroll
@@ -658,7 +670,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             const int code = locate(xt, ext, c, u);
             if (code != ccode) {
                 ccode = code;
-                fetch_corners(A.psi, A.nx, A.ny, A.nz, A.px, A.py, A.pz, gi, gj, gk, c, cw);
+                float2 w[8];
+                fetch_corners(A.psi, A.nx, A.ny, A.nz, A.px, A.py, A.pz, gi, gj, gk, c, w);
+                tri_coeffs(w, cw);
             }
             trilinear(cw, u, tr, ti, tgr, tgi);
         };
