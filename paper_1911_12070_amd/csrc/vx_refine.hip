@@ -1,20 +1,23 @@
 // Core-sample refinement (Sec. 3.3.1 mean-position estimate, Sec. 3.3.3 density-guided minimisation
 // in the plane normal to the pseudo-vorticity, psi linearly interpolated between nodes as in Sec. 5).
 //
-// Work layout. The number of listed cells is read on the device (no host synchronisation); the
-// list is cut into chunks of REF_CHUNK samples that wavefronts claim from a device counter (zeroed
-// by a one-thread kernel on the same stream before each launch). The iteration count per sample
-// varies a lot (median about 9 accepted steps, a long tail past 30), so lanes do not take one
-// sample each in lockstep: every lane runs its own sample as a state machine that performs one trilinear
-// evaluation per pass of the wave's loop, and a lane whose sample is done writes it and takes the
-// next unclaimed sample of the wave's chunk (ballot + mbcnt, the claim cursor is wave-uniform).
-// The wave thus pays for the mean iteration count of its samples, not for the maximum over 64.
+// Work layout. The number of listed cells is read on the device (no host synchronisation), so every
+// call launches two kernels and the one whose list it is not returns at once: refine_spec_k for
+// lists of at most one sample per resident 16-lane group (described with that kernel below), and
+// refine_k for longer ones. refine_k cuts the list into chunks of REF_CHUNK samples that wavefronts
+// claim from a device counter (zeroed by refine_spec_k, which runs first on the same stream). The
+// iteration count per sample varies a lot (median about 9 accepted steps, a long tail past 30), so
+// lanes do not take one sample each in lockstep: every lane runs its own sample as a state machine
+// that performs one trilinear evaluation per pass of the wave's loop, and a lane whose sample is done
+// writes it and takes the next unclaimed sample of the wave's chunk (ballot + mbcnt, the claim
+// cursor is wave-uniform). The wave thus pays for the mean iteration count of its samples, not for
+// the maximum over 64.
 //
-// The iterate only needs the 8 corners of the unit cell that holds it; they are cached per lane in
-// LDS and fetched from global memory (L1/L2-resident: neighbouring samples share nodes) when the
-// iterate changes cell. The state machine's bookkeeping after each evaluation is written as selects:
-// loop-carried state updated under divergent branches costs register copies at every merge.
-// FP32 arithmetic throughout.
+// The iterate only needs the 8 corners of the unit cell that holds it; their interpolation
+// polynomial is cached per lane in LDS and rebuilt from global memory (L1/L2-resident: neighbouring
+// samples share nodes) when the iterate changes cell. The state machine's bookkeeping after each
+// evaluation is written as selects: loop-carried state updated under divergent branches costs
+// register copies at every merge. FP32 arithmetic throughout.
 #include "vx_internal.h"
 
 namespace {
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
 // a time. Every lane of a group holds the sample's state. The arithmetic is refine_k's: the shared
 // functions above, the same expressions for the trial point and the acceptance tests, and halvings
 // as the same sequence of exact multiplications by 1/2, so the samples are bit-identical to refine_k's.
-// A lane keeps the corners of the cell of its last evaluation in registers.
+// A lane keeps the interpolation coefficients of the cell of its last evaluation in registers.
 constexpr int SPEC_G = 16;
 
 __device__ __forceinline__ float halve_n(float a, int n) {  // n multiplications by 0.5f, n in [0, SPEC_G]
