@@ -716,13 +716,15 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // The barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell
 // ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
-                                                   const int64_t *__restrict__ count, int64_t cap, float4 *net_out) {
+                                                   const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
+                                                   int64_t *fb_count) {
     constexpr int NW = NTI / 64;
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
     __shared__ float2 sg[GT];
     __shared__ __attribute__((aligned(16))) float sB[2 * NH];          // b1 then b2
     __shared__ __attribute__((aligned(16))) float sP[NW * TM * NOUT];  // partial heads [wavefront][cell][4]
+    if (blockIdx.x == 0 && threadIdx.x == 0) *fb_count = 0;  // the fallback queue of polish_k, launched next
     const int64_t n = min(*count, cap);
     const int64_t ntiles = (n + TM - 1) / TM;
     if ((int64_t)blockIdx.x >= ntiles) return;  // uniform per workgroup
@@ -920,8 +922,6 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
         }
     }
 }
-
-__global__ void zero_i64_k(int64_t *p) { *p = 0; }
 
 }  // namespace
 
@@ -1237,11 +1237,11 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     }
     hipStream_t hs = (hipStream_t)s;
     vx_timer tm(h, hs, VX_KIND_MLP);
-    hipLaunchKernelGGL(zero_i64_k, dim3(1), dim3(1), 0, hs, m->fb_count);
+    const int64_t num_cu = h->num_cu > 0 ? h->num_cu : 256;
     const int64_t tiles = (cap + TM - 1) / TM;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, h->num_cu > 0 ? h->num_cu : 256));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu));
     hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
-                       d_count, cap, m->net_out);
+                       d_count, cap, m->net_out, m->fb_count);
     tm.stop();
     vx_timer tp(h, hs, VX_KIND_POLISH);
     hipLaunchKernelGGL(polish_k, dim3((unsigned)((cap + NT - 1) / NT)), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
