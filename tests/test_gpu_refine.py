@@ -190,3 +190,41 @@ def test_short_list_bit_identical(ex, periodic):
     ex.refine(psi, sub, periodic, marker)
     torch.cuda.synchronize()
     assert bool((marker == 7).all())
+
+
+@pytest.mark.parametrize("variant", ["newton_only", "few_halvings", "one_newton", "long_steps", "no_descent_no_newton"])
+def test_short_list_bit_identical_params(ex, variant):
+    """The two refinement kernels agree bit for bit under non-default step rules too (descent
+    disabled, at most two halvings per step, one Newton step, longer trial steps, no steps at all):
+    the 256^3 tangle's full list against a random subset of it."""
+    import torch
+    from paper_1911_12070_amd import samples_to_numpy, vx_refine_defaults
+    p = vx_refine_defaults()
+    if variant == "newton_only":
+        p.max_descent = 0
+    elif variant == "few_halvings":
+        p.max_halvings = 2
+    elif variant == "one_newton":
+        p.max_newton = 1
+    elif variant == "long_steps":
+        p.step0 = 0.9
+        p.step_max = 2.0
+    else:
+        p.max_descent = 0
+        p.max_newton = 0
+    psi = ex.gen_tangle(vxinputs.tangle_256())
+    nz, ny, nx = psi.shape
+    out = ex.alloc_winding(psi.shape, face_cap=nx * ny * nz // 16, cell_cap=nx * ny * nz // 16, wind=False)
+    ex.winding(psi, 7, out)
+    torch.cuda.synchronize()
+    nc = int(out["counts"][1].cpu())
+    assert nc > 40_000
+    full = samples_to_numpy(ex.refine(psi, out, 7, params=p), nc)
+    idx = np.sort(np.random.default_rng(9).choice(nc, 3000, replace=False))
+    sel = torch.from_numpy(idx.astype(np.int64)).cuda()
+    sub = {"cells": out["cells"][sel].contiguous(), "cdesc": out["cdesc"][sel].contiguous(),
+           "counts": torch.tensor([0, len(idx)], dtype=torch.int64, device="cuda")}
+    got = samples_to_numpy(ex.refine(psi, sub, 7, params=p), len(idx))
+    torch.cuda.synchronize()
+    log(f"{variant}: iters max {int(full['iters'].max())}, status bits {sorted(set(int(v) for v in full['status']))[:8]}")
+    assert got.tobytes() == full[idx].tobytes()
