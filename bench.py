@@ -119,6 +119,43 @@ def bench_surrogate(ex):
     return r
 
 
+def bench_pipeline(ex, psi, steps: int, warmup: int, cap: int, wl: str, N: int):
+    """The same frames as a stream: the winding of frame k runs on one stream while frame k-1 is
+    refined on another (FramePipeline; same kernels, same results). Timed from the first winding
+    to the last refinement of `steps` frames, pipeline fill and drain included."""
+    import torch
+
+    from paper_1911_12070_amd import KIND_REFINE, KIND_WIND, FramePipeline, vx_profile_enable, vx_profile_read
+    print("[bench] frame pipeline (winding of frame k beside the refinement of frame k-1)", file=sys.stderr,
+          flush=True)
+    pipe = FramePipeline(ex, psi.shape, cap, cap)
+    for _ in range(max(warmup, 2)):
+        pipe.push(psi)
+    pipe.sync()
+    torch.cuda.synchronize()
+    vx_profile_enable(ex.h, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.push(psi)
+    pipe.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    wind_ms, nw = vx_profile_read(ex.h, KIND_WIND)
+    ref_ms, nr = vx_profile_read(ex.h, KIND_REFINE)
+    vx_profile_enable(ex.h, False)
+    del pipe
+    torch.cuda.empty_cache()
+    return {
+        "value": N ** 3 * steps / elapsed,
+        "unit": "cells/s",
+        "frames": steps,
+        "ms_per_frame": 1e3 * elapsed / steps,
+        "kernel_ms_while_overlapped": {"wind_compact": wind_ms / max(nw, 1), "refine": ref_ms / max(nr, 1)},
+        "workload": f"{wl} as a stream of frames: winding of frame k on one HIP stream beside the refinement "
+                    "of frame k-1 on another, two alternating output buffer sets",
+    }
+
+
 def calib_copy():
     """Kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
     (fill: writes 1 GiB; sum: reads 1 GiB)."""
@@ -349,7 +386,10 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
-    del psi, out, samples
+    del out, samples
+    torch.cuda.empty_cache()
+    res["pipelined"] = bench_pipeline(ex, psi, args.steps, args.warmup, cap, wl, N)
+    del psi
     torch.cuda.empty_cache()
     res["surrogate"] = bench_surrogate(ex)
     if not args.no_cpu_baseline:

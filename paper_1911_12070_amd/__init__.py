@@ -376,4 +376,4 @@ def vx_profile_read(h, kind: int):
     return ms.value, n.value
 
 
-from .pipeline import Batch, Extractor, upload_tangle, samples_to_numpy  # noqa: E402,F401
+from .pipeline import Batch, Extractor, FramePipeline, upload_tangle, samples_to_numpy  # noqa: E402,F401

@@ -236,9 +236,13 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
     // sign words of this lane's row from the plane in LDS
     auto sign_words = [&](uint32_t &pi, uint32_t &nr, uint32_t &pih, uint32_t &nrh) {
         uint32_t a = 0, b = 0;
+        // the 16 read offsets are recomputed per plane rather than kept in registers: at <= 192
+        // VGPRs two winding wavefronts per SIMD leave room for a refinement wavefront of another
+        // frame to run beside them
+        const int rr = (int)pin((uint32_t)r), cq = (int)pin((uint32_t)c);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const float4 v = *reinterpret_cast<const float4 *>(s_plane + piece_off(r, 16 * c + i));
+            const float4 v = *reinterpret_cast<const float4 *>(s_plane + piece_off(rr, 16 * cq + i));
             a |= (v.y > 0.0f ? 1u : 0u) << (2 * i);
             a |= (v.w > 0.0f ? 1u : 0u) << (2 * i + 1);
             b |= (v.x < 0.0f ? 1u : 0u) << (2 * i);

@@ -169,3 +169,52 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class FramePipeline:
+    """Winding and refinement of a stream of same-shape frames on two streams, so that the winding
+    of frame k runs while frame k-1 is refined: the winding is bound by HBM, the refinement by
+    vector issue, and the two kernels fit side by side on every CU. Two sets of output buffers
+    alternate; frame k's results are in slot push(k) returned, valid once `done(slot)` has been
+    waited for (or after `sync()`), and until frame k+2 is pushed. Every psi tensor must stay alive
+    until its frame is done. All calls go to one handle, which must not be used by other work
+    while frames are in flight (the refinements share its chunk counter, on one stream)."""
+
+    def __init__(self, ex: Extractor, shape, face_cap: int, cell_cap: int, wind: bool = True,
+                 periodic: int = 7, params=None):
+        torch = ex.torch
+        self.ex = ex
+        self.periodic = periodic
+        self.params = params
+        self.outs = [ex.alloc_winding(shape, face_cap=face_cap, cell_cap=cell_cap, wind=wind) for _ in range(2)]
+        self.samples = [ex.alloc_samples(cell_cap) for _ in range(2)]
+        dev = torch.device("cuda", ex.device)
+        self.s_wind = torch.cuda.Stream(device=dev)
+        self.s_refine = torch.cuda.Stream(device=dev)
+        self._refined = [None, None]
+        self.k = 0
+
+    def push(self, psi) -> int:
+        """Enqueue the next frame; returns its output slot (0 or 1)."""
+        torch = self.ex.torch
+        b = self.k % 2
+        if self._refined[b] is not None:  # frame k-2 has finished with this slot
+            self.s_wind.wait_event(self._refined[b])
+        self.ex.winding(psi, self.periodic, self.outs[b], self.s_wind)
+        wound = torch.cuda.Event()
+        wound.record(self.s_wind)
+        self.s_refine.wait_event(wound)
+        self.ex.refine(psi, self.outs[b], self.periodic, self.samples[b], self.params, None, self.s_refine)
+        refined = torch.cuda.Event()
+        refined.record(self.s_refine)
+        self._refined[b] = refined
+        self.k += 1
+        return b
+
+    def done(self, slot: int):
+        """Event recorded after the last refinement written to `slot` (None before any)."""
+        return self._refined[slot]
+
+    def sync(self):
+        self.s_wind.synchronize()
+        self.s_refine.synchronize()
