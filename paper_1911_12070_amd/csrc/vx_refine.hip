@@ -107,32 +107,36 @@ __device__ __forceinline__ V3 first_estimate(uint32_t desc, uint32_t &status) {
     return v3(sx * inv, sy * inv, sz * inv);
 }
 
-// patch extent of the cell at node (gi, gj, gk): bit a set if the patch reaches -1 on axis a, bit
-// 3 + a set if it reaches +2 (else it stops at 0 / +1)
-__device__ __forceinline__ uint32_t patch_ext(int gi, int gj, int gk, int nx, int ny, int nz, int px, int py, int pz) {
+// The node patch of a sample, in the cell's local coordinates: [lo, hc + 1] per axis, where lo is
+// -1 if the patch reaches one node below the cell (else 0) and hc is 1 if it reaches two nodes above
+// (else 0) -- the cells of the patch are lo .. hc. Kept as floats so that the per-pass tests need no
+// decoding.
+struct Box {
+    V3 lo, hc;
+};
+
+__device__ __forceinline__ Box patch_box(int gi, int gj, int gk, int nx, int ny, int nz, int px, int py, int pz) {
     const int g3[3] = {gi, gj, gk};
     const int n3[3] = {nx, ny, nz};
     const int p3[3] = {px, py, pz};
-    uint32_t ext = 0;
+    float lo[3], hc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (p3[a] || g3[a] - 1 >= 0) ext |= 1u << a;
-        if (p3[a] || g3[a] + 2 < n3[a]) ext |= 8u << a;
+        lo[a] = (p3[a] || g3[a] - 1 >= 0) ? -1.f : 0.f;
+        hc[a] = (p3[a] || g3[a] + 2 < n3[a]) ? 1.f : 0.f;
     }
-    return ext;
+    return Box{v3(lo[0], lo[1], lo[2]), v3(hc[0], hc[1], hc[2])};
 }
 
 // the patch cell that holds point x (clamped to the patch) and the local coordinates in it;
 // returns the cell's code (cx+1) + 4 (cy+1) + 16 (cz+1)
-__device__ __forceinline__ int locate(const V3 &x, uint32_t ext, int c[3], float u[3]) {
-    const float xs[3] = {x.x, x.y, x.z};
+__device__ __forceinline__ int locate(const V3 &x, const Box &b, int c[3], float u[3]) {
+    const float xs[3] = {x.x, x.y, x.z}, lo[3] = {b.lo.x, b.lo.y, b.lo.z}, hc[3] = {b.hc.x, b.hc.y, b.hc.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int lo = (ext >> a) & 1u ? -1 : 0, hi = (ext >> (3 + a)) & 1u ? 1 : 0;
-        int fl = (int)floorf(xs[a]);
-        fl = max(lo, min(fl, hi));
-        c[a] = fl;
-        u[a] = xs[a] - (float)fl;
+        const float fl = fminf(fmaxf(floorf(xs[a]), lo[a]), hc[a]);
+        c[a] = (int)fl;
+        u[a] = xs[a] - fl;
     }
     return (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
 }
@@ -241,11 +245,9 @@ __device__ __forceinline__ V3 plane_point(const V3 &x0, const V3 &e1, const V3 &
     return v3(x0.x + y1 * e1.x + y2 * e2.x, x0.y + y1 * e1.y + y2 * e2.y, x0.z + y1 * e1.z + y2 * e2.z);
 }
 
-__device__ __forceinline__ bool in_patch(const V3 &x, uint32_t ext) {
-    const float lx = (ext & 1u) ? -1.f : 0.f, ly = (ext & 2u) ? -1.f : 0.f;
-    const float lz = (ext & 4u) ? -1.f : 0.f, hx = (ext & 8u) ? 2.f : 1.f;
-    const float hy = (ext & 16u) ? 2.f : 1.f, hz = (ext & 32u) ? 2.f : 1.f;
-    return x.x >= lx && x.x <= hx && x.y >= ly && x.y <= hy && x.z >= lz && x.z <= hz;
+__device__ __forceinline__ bool in_patch(const V3 &x, const Box &b) {
+    return x.x >= b.lo.x && x.x <= b.hc.x + 1.f && x.y >= b.lo.y && x.y <= b.hc.y + 1.f && x.z >= b.lo.z &&
+           x.z <= b.hc.z + 1.f;
 }
 
 // steepest descent of |psi|^2 in the plane: direction (n1, n2) * den = -g / |g|, gn = |g|
@@ -368,8 +370,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     uint64_t cell = 0;
     uint32_t desc = 0;
     int gi = 0, gj = 0, gk = 0;  // grid node of the sample cell's min corner
-    uint32_t ext = 0;            // patch extent: bit a set if the patch reaches -1 on axis a,
-                                 // bit 3 + a set if it reaches +2 (else it stops at 0 / +1)
+    Box box{};                   // the sample's node patch
     int ccode = -1;              // cached cell: (cx+1) + 4 (cy+1) + 16 (cz+1)
     V3 x0 = v3(0.f, 0.f, 0.f), e1 = x0, e2 = x0, xt = x0;
     float y1 = 0.f, y2 = 0.f, ty1 = 0.f, ty2 = 0.f;
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                         gk = (int)divmod53(cell, nxy, rnxy, rxy);
                         gj = (int)divmod53(rxy, nx64, rnx, ri);
                         gi = (int)ri;
-                        ext = patch_ext(gi, gj, gk, fnx, fny, fnz, fpx, fpy, fpz);
+                        box = patch_box(gi, gj, gk, fnx, fny, fnz, fpx, fpy, fpz);
                         ccode = -1;  // force a corner fetch at the first evaluation
                         status = 0;
                         iters = 0;
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         if (phase != PH_IDLE) {
             int c[3];
             float u[3];
-            const int code = locate(xt, ext, c, u);
+            const int code = locate(xt, box, c, u);
             if (code != ccode) {
                 ccode = code;
                 const float2 *psi_p = A.psi;
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                 ty1 = y1 + alpha * p1;
                 ty2 = y2 + alpha * p2;
                 xt = plane_point(x0, e1, e2, ty1, ty2);
-                if (in_patch(xt, ext)) {
+                if (in_patch(xt, box)) {
                     // a Newton trial point equal to the current point (as is then every shorter
                     // one) is rejected at this and every remaining halving: |psi|^2 cannot decrease
                     if (mode == MODE_NEWTON && ty1 == y1 && ty2 == y2) stuck = true;
@@ -661,7 +662,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         const int gk = (int)divmod53(cell, nxy, rnxy, rxy);
         const int gj = (int)divmod53(rxy, nx64, rnx, ri);
         const int gi = (int)ri;
-        const uint32_t ext = patch_ext(gi, gj, gk, A.nx, A.ny, A.nz, A.px, A.py, A.pz);
+        const Box box = patch_box(gi, gj, gk, A.nx, A.ny, A.nz, A.px, A.py, A.pz);
         uint32_t status = 0;
         V3 x0 = first_estimate(desc, status);
         if (A.seed) x0 = v3(A.seed[3 * s], A.seed[3 * s + 1], A.seed[3 * s + 2]);
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         auto eval = [&](const V3 &xt, float &tr, float &ti, V3 &tgr, V3 &tgi) {
             int c[3];
             float u[3];
-            const int code = locate(xt, ext, c, u);
+            const int code = locate(xt, box, c, u);
             if (code != ccode) {
                 ccode = code;
                 float2 w[8];
@@ -727,7 +728,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             const float ty2 = y2 + a * p2;
             const V3 xt = plane_point(x0, e1, e2, ty1, ty2);
             const bool valid = hv + h < P.max_halvings;
-            const bool inside = valid && in_patch(xt, ext);
+            const bool inside = valid && in_patch(xt, box);
             const bool stuck = inside && mode == MODE_NEWTON && ty1 == y1 && ty2 == y2;
             tr = 0.f;
             ti = 0.f;
