@@ -250,6 +250,11 @@ __device__ __forceinline__ bool in_patch(const V3 &x, const Box &b) {
            x.z <= b.hc.z + 1.f;
 }
 
+// the accepted Newton step alpha (p1, p2) is shorter than tol (compared squared: no square root)
+__device__ __forceinline__ bool newton_short(float alpha, float p1, float p2, float tol) {
+    return alpha * alpha * (p1 * p1 + p2 * p2) < tol * tol;
+}
+
 // steepest descent of |psi|^2 in the plane: direction (n1, n2) * den = -g / |g|, gn = |g|
 __device__ __forceinline__ bool descent_dir(float vr, float vi, const V3 &gr, const V3 &gim, const V3 &e1,
                                             const V3 &e2, float &n1, float &n2, float &den, float &gn) {
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         dit += acc_d ? 1 : 0;
         nit += acc_n ? 1 : 0;
         s_prev = acc_d ? alpha : s_prev;
-        const bool conv_now = acc_n && alpha * sqrtf(p1 * p1 + p2 * p2) < P.newton_tol;
+        const bool conv_now = acc_n && newton_short(alpha, p1, p2, P.newton_tol);
         converged = converged || conv_now;
         mode = (acc_d && alpha < P.descent_tol) ? MODE_NEWTON : mode;
         const bool rej = tri && !acc;
@@ -761,7 +766,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
                     } else {
                         ++nit;
                     }
-                    const bool conv_now = !descent && aa * sqrtf(p1 * p1 + p2 * p2) < P.newton_tol;
+                    const bool conv_now = !descent && newton_short(aa, p1, p2, P.newton_tol);
                     converged = converged || conv_now;
                     if (descent && aa < P.descent_tol) mode = MODE_NEWTON;
                     if (conv_now) done = true;
