@@ -383,7 +383,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     V3 gr = x0, gim = x0;
     float s_prev = 0.f, gn = 0.f;           // descent: last accepted length, gradient norm
     float alpha = 0.f, p1 = 0.f, p2 = 0.f;  // current step: length factor and direction
-    int dit = 0, nit = 0, hv = 0, iters = 0;
+    int dit = 0, nit = 0, hv = 0;  // accepted descent and Newton steps (their sum is reported), halvings
     uint32_t status = 0;
     bool converged = false;
 
@@ -445,7 +445,6 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                         box = patch_box(gi, gj, gk, fnx, fny, fnz, fpx, fpy, fpz);
                         ccode = -1;  // force a corner fetch at the first evaluation
                         status = 0;
-                        iters = 0;
                         dit = 0;
                         nit = 0;
                         converged = false;
@@ -525,7 +524,6 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         gim.y = take ? tgi.y : gim.y;
         gim.z = take ? tgi.z : gim.z;
         f = take ? ft : f;
-        iters += acc ? 1 : 0;
         const bool acc_d = acc && descent, acc_n = acc && !descent;
         dit += acc_d ? 1 : 0;
         nit += acc_n ? 1 : 0;
@@ -610,7 +608,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             o.off[1] = xe.y;
             o.off[2] = xe.z;
             o.rho = f;
-            o.iters = (uint16_t)min(iters, 65535);
+            o.iters = (uint16_t)min(dit + nit, 65535);
             o.status = (uint16_t)status;
             o.reserved = 0;
             if constexpr (BATCH) s_fr[fr].out[s] = o;
@@ -695,7 +693,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         float f = tr * tr + ti * ti;
         float s_prev = 0.5f * P.step0, gn = 0.f;
         float alpha = 0.f, p1 = 0.f, p2 = 0.f;  // current step: length at halving hv, direction
-        int mode = MODE_DESCENT, dit = 0, nit = 0, hv = 0, iters = 0;
+        int mode = MODE_DESCENT, dit = 0, nit = 0, hv = 0;
         bool converged = false, done = false;
         // start a step of the current kind (a descent that cannot start hands over to Newton at
         // once), or end the sample
@@ -759,7 +757,6 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
                     gr = v3(__shfl(tgr.x, src), __shfl(tgr.y, src), __shfl(tgr.z, src));
                     gim = v3(__shfl(tgi.x, src), __shfl(tgi.y, src), __shfl(tgi.z, src));
                     f = __shfl(ft, src);
-                    ++iters;
                     if (descent) {
                         ++dit;
                         s_prev = aa;
@@ -796,7 +793,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             o.off[1] = xe.y;
             o.off[2] = xe.z;
             o.rho = f;
-            o.iters = (uint16_t)min(iters, 65535);
+            o.iters = (uint16_t)min(dit + nit, 65535);
             o.status = (uint16_t)status;
             o.reserved = 0;
             *dst = o;
