@@ -282,6 +282,14 @@ __device__ __forceinline__ bool newton_dir(float vr, float vi, const V3 &gr, con
     return det != 0.f && fabsf(idet) < INFINITY;
 }
 
+// a wavefront-uniform 64-bit value, made visibly uniform to the compiler (so that loops and
+// branches on it stay scalar)
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // lane phases
 constexpr int PH_IDLE = 0;     // no sample
 constexpr int PH_INIT = 1;     // pending evaluation at the first estimate x0
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     const vx_refine_params &P = A.p;
     const int tid = threadIdx.x;
     const int64_t nwaves = (int64_t)gridDim.x * (REF_THREADS / 64);
-    const int64_t wave = (int64_t)blockIdx.x * (REF_THREADS / 64) + (tid >> 6);
+    const int64_t wave = (int64_t)blockIdx.x * (REF_THREADS / 64) + __builtin_amdgcn_readfirstlane(tid >> 6);
     int64_t n_items = 0;  // single grid: number of samples
     if constexpr (BATCH) {
         // frame table, samples per frame and the prefix of chunks per frame
@@ -354,9 +362,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                 if (s_cstart[mid] <= ci) lo = mid;
                 else hi = mid;
             }
-            cf = lo;
-            next = (ci - s_cstart[lo]) * REF_CHUNK;
-            end = min(s_items[lo], next + REF_CHUNK);
+            cf = __builtin_amdgcn_readfirstlane(lo);
+            next = uni64((ci - s_cstart[cf]) * REF_CHUNK);
+            end = uni64(min(s_items[cf], next + REF_CHUNK));
         } else {
             next = min(n_items, ci * chunk);
             end = min(n_items, next + chunk);
