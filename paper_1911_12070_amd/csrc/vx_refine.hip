@@ -465,10 +465,11 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
             }
             next += (int64_t)n_idle;
         }
-        if (__ballot(phase != PH_IDLE) == 0) {
-            if (next >= end && !more) break;
-            continue;  // nothing claimed yet, or every claimed id was out of range: claim again
-        }
+        // all lanes idle with nothing left to claim: done. All lanes idle otherwise (nothing claimed
+        // yet, or every claimed id out of range) runs the pass below, which leaves idle lanes as they
+        // are, and claims again; a second path back to the loop's head would cost a register copy of
+        // every loop-carried variable per pass
+        if (next >= end && !more && __ballot(phase != PH_IDLE) == 0) break;
 
         // ---- one trilinear evaluation at the pending point (value and gradient, cell units); lanes
         // waiting to begin a step evaluate too (a point of their patch) and ignore the result
