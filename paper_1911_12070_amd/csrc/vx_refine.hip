@@ -59,10 +59,12 @@ __device__ __forceinline__ int dec2(uint32_t d, int f) {
     return v == 1u ? 1 : (v == 3u ? -1 : 0);
 }
 
-__device__ __forceinline__ int64_t wrap(int64_t q, int n, int per) {
-    if (q < 0) return per ? q + n : 0;
-    if (q >= n) return per ? q - n : n - 1;
-    return q;
+// node g + c of an axis of n nodes (g in [0, n), c in [-1, 2]): wrapped if the axis is periodic,
+// else clamped. In 32-bit unsigned arithmetic, where g + c = -1 is the only value above 2^31.
+__device__ __forceinline__ uint32_t wrap(int g, int c, int n, int per) {
+    const uint32_t q = (uint32_t)g + (uint32_t)c, un = (uint32_t)n;
+    const uint32_t below = per ? un - 1u : 0u, above = per ? q - un : un - 1u;
+    return q == 0xffffffffu ? below : (q >= un ? above : q);
 }
 
 // quotient and remainder of n by d for n < 2^53 (every cell id of a grid that fits in memory):
@@ -145,12 +147,9 @@ __device__ __forceinline__ int locate(const V3 &x, const Box &b, int c[3], float
 __device__ __forceinline__ void fetch_corners(const float2 *psi_p, int fnx, int fny, int fnz, int fpx, int fpy,
                                               int fpz, int gi, int gj, int gk, const int c[3], float2 v[8]) {
     const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
-    const int64_t i0 = wrap((int64_t)gi + c[0], fnx, fpx);
-    const int64_t i1 = wrap((int64_t)gi + c[0] + 1, fnx, fpx);
-    const int64_t j0 = wrap((int64_t)gj + c[1], fny, fpy);
-    const int64_t j1 = wrap((int64_t)gj + c[1] + 1, fny, fpy);
-    const int64_t k0 = wrap((int64_t)gk + c[2], fnz, fpz);
-    const int64_t k1 = wrap((int64_t)gk + c[2] + 1, fnz, fpz);
+    const uint32_t i0 = wrap(gi, c[0], fnx, fpx), i1 = wrap(gi, c[0] + 1, fnx, fpx);
+    const uint32_t j0 = wrap(gj, c[1], fny, fpy), j1 = wrap(gj, c[1] + 1, fny, fpy);
+    const uint32_t k0 = wrap(gk, c[2], fnz, fpz), k1 = wrap(gk, c[2] + 1, fnz, fpz);
     const float2 *r00 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
     const float2 *r10 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
     const float2 *r01 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
@@ -394,6 +393,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     int dit = 0, nit = 0, hv = 0;  // accepted descent and Newton steps (their sum is reported), halvings
     uint32_t status = 0;
     bool converged = false;
+    // the latest evaluation (value and gradient); an idle lane keeps stale values, which it never reads
+    float tr = 0.f, ti = 0.f;
+    V3 tgr = x0, tgi = x0;
 
     while (true) {
         // ---- idle lanes claim the next samples of the wave's range, once enough of them are idle
@@ -473,8 +475,6 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
 
         // ---- one trilinear evaluation at the pending point (value and gradient, cell units); lanes
         // waiting to begin a step evaluate too (a point of their patch) and ignore the result
-        float tr = 0.f, ti = 0.f;
-        V3 tgr = v3(0.f, 0.f, 0.f), tgi = tgr;
         if (phase != PH_IDLE) {
             int c[3];
             float u[3];
