@@ -254,11 +254,21 @@ __device__ __forceinline__ bool newton_short(float alpha, float p1, float p2, fl
     return alpha * alpha * (p1 * p1 + p2 * p2) < tol * tol;
 }
 
-// steepest descent of |psi|^2 in the plane: direction (n1, n2) * den = -g / |g|, gn = |g|
-__device__ __forceinline__ bool descent_dir(float vr, float vi, const V3 &gr, const V3 &gim, const V3 &e1,
-                                            const V3 &e2, float &n1, float &n2, float &den, float &gn) {
-    const V3 G = v3(2.f * (vr * gr.x + vi * gim.x), 2.f * (vr * gr.y + vi * gim.y), 2.f * (vr * gr.z + vi * gim.z));
-    const float g1 = dot(e1, G), g2 = dot(e2, G);
+// the gradients of Re psi and Im psi in the plane: J = [[e1.gr, e2.gr], [e1.gim, e2.gim]], the
+// Jacobian of (Re psi, Im psi) with respect to the in-plane coordinates (y1, y2); both step kinds
+// start from it
+struct PlaneJ {
+    float j00, j01, j10, j11;
+};
+__device__ __forceinline__ PlaneJ plane_jac(const V3 &gr, const V3 &gim, const V3 &e1, const V3 &e2) {
+    return PlaneJ{dot(e1, gr), dot(e2, gr), dot(e1, gim), dot(e2, gim)};
+}
+
+// steepest descent of |psi|^2 in the plane: gradient g = 2 J^T psi, direction (n1, n2) * den = -g / |g|,
+// gn = |g|
+__device__ __forceinline__ bool descent_dir(float vr, float vi, const PlaneJ &J, float &n1, float &n2, float &den,
+                                            float &gn) {
+    const float g1 = 2.f * (vr * J.j00 + vi * J.j10), g2 = 2.f * (vr * J.j01 + vi * J.j11);
     const float gg = g1 * g1 + g2 * g2;
     const float ig = rsq(gg);
     gn = gg * ig;
@@ -269,10 +279,8 @@ __device__ __forceinline__ bool descent_dir(float vr, float vi, const V3 &gr, co
 }
 
 // Newton step for (Re psi, Im psi) = 0 in the plane: direction (n1, n2) * den = -J^-1 psi
-__device__ __forceinline__ bool newton_dir(float vr, float vi, const V3 &gr, const V3 &gim, const V3 &e1,
-                                           const V3 &e2, float &n1, float &n2, float &den) {
-    const float j00 = dot(e1, gr), j01 = dot(e2, gr);
-    const float j10 = dot(e1, gim), j11 = dot(e2, gim);
+__device__ __forceinline__ bool newton_dir(float vr, float vi, const PlaneJ &J, float &n1, float &n2, float &den) {
+    const float j00 = J.j00, j01 = J.j01, j10 = J.j10, j11 = J.j11;
     const float det = j00 * j11 - j01 * j10;
     const float idet = rcp(det);
     n1 = -(j11 * vr - j01 * vi);
@@ -552,9 +560,10 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         if (begin) {
             float n1 = 0.f, n2 = 0.f, den = 1.f;  // direction = (n1, n2) * den
             bool ok = false;
+            const PlaneJ J = plane_jac(gr, gim, e1, e2);
             if (mode == MODE_DESCENT) {
                 if (dit < P.max_descent && f != 0.f) {
-                    ok = descent_dir(vr, vi, gr, gim, e1, e2, n1, n2, den, gn);
+                    ok = descent_dir(vr, vi, J, n1, n2, den, gn);
                     alpha = fminf(2.f * s_prev, P.step_max);
                 }
                 if (!ok) {
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                     if (f == 0.f) {
                         converged = true;
                     } else {
-                        ok = newton_dir(vr, vi, gr, gim, e1, e2, n1, n2, den);
+                        ok = newton_dir(vr, vi, J, n1, n2, den);
                         alpha = 1.f;
                     }
                 }
@@ -709,9 +718,10 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         auto begin = [&]() {
             float n1 = 0.f, n2 = 0.f, den = 1.f;
             bool ok = false;
+            const PlaneJ J = plane_jac(gr, gim, e1, e2);
             if (mode == MODE_DESCENT) {
                 if (dit < P.max_descent && f != 0.f) {
-                    ok = descent_dir(vr, vi, gr, gim, e1, e2, n1, n2, den, gn);
+                    ok = descent_dir(vr, vi, J, n1, n2, den, gn);
                     alpha = fminf(2.f * s_prev, P.step_max);
                 }
                 if (!ok) mode = MODE_NEWTON;
@@ -721,7 +731,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
                     if (f == 0.f) {
                         converged = true;
                     } else {
-                        ok = newton_dir(vr, vi, gr, gim, e1, e2, n1, n2, den);
+                        ok = newton_dir(vr, vi, J, n1, n2, den);
                         alpha = 1.f;
                     }
                 }
