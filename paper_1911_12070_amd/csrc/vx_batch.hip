@@ -313,26 +313,39 @@ extern "C" vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_s
     const bool prof = h->profile;
     h->profile = false;  // tuning launches are not part of the caller's timing
     vx_status st = VX_OK;
-    for (const Key &k : todo) {
-        int best_zc = 0;
-        double best = 1e30;
-        for (int cand : candidates(k[2])) {
-            for (size_t f = 0; f < b->frames.size(); ++f)
-                if (key_of(b->frames[f].dims) == k) b->zc[f] = cand;
-            st = upload(b);
-            double ms = 0.0;
-            if (st == VX_OK) st = time_median(h, hs, 3, [&] { return enqueue_wind(b, hs); }, &ms);
-            if (st) break;
-            if (ms < best) {
-                best = ms;
-                best_zc = cand;
+    // coordinate descent over the frame sizes, timing the whole batch's winding: each size takes the
+    // depth that is fastest with the others at their current depths; a second sweep revisits every
+    // size once the others have settled (the gain of one size's depth is a small part of the batch)
+    std::map<Key, double> best_ms;
+    for (int sweep = 0; sweep < 2 && st == VX_OK; ++sweep) {
+        for (const Key &k : todo) {
+            int best_zc = 0;
+            double best = 1e30;
+            for (int cand : candidates(k[2])) {
+                for (size_t f = 0; f < b->frames.size(); ++f)
+                    if (key_of(b->frames[f].dims) == k) b->zc[f] = cand;
+                st = upload(b);
+                double ms = 0.0;
+                if (st == VX_OK) st = time_median(h, hs, 7, [&] { return enqueue_wind(b, hs); }, &ms);
+                if (st) break;
+                if (ms < best) {
+                    best = ms;
+                    best_zc = cand;
+                }
             }
+            if (st) break;
+            for (size_t f = 0; f < b->frames.size(); ++f)
+                if (key_of(b->frames[f].dims) == k) b->zc[f] = best_zc;
+            best_ms[k] = best;
         }
-        if (st) break;
-        for (size_t f = 0; f < b->frames.size(); ++f)
-            if (key_of(b->frames[f].dims) == k) b->zc[f] = best_zc;
-        append_cache(cache_path, "batch", k, best_zc, best);
     }
+    if (st == VX_OK)
+        for (const Key &k : todo) {
+            int zc = 0;
+            for (size_t f = 0; f < b->frames.size(); ++f)
+                if (key_of(b->frames[f].dims) == k) zc = b->zc[f];
+            append_cache(cache_path, "batch", k, zc, best_ms[k]);
+        }
     h->profile = prof;
     if (st == VX_OK) st = upload(b);
     if (st == VX_OK) st = capture(b);

@@ -158,12 +158,9 @@ __device__ __forceinline__ void first_estimate(uint32_t desc, float &x, float &y
     }
 }
 
-// trilinear psi and its gradient (cell units) at cell-local x, from the corners of the patch cell
-// that holds x (clamped to the 3x3x3 cells of the patch), FP32, read from the field
-__device__ __forceinline__ void tri_eval(const Geo &g, int i, int j, int k, const float x[3], float &vr, float &vi,
-                                         float gr[3], float gi[3]) {
-    int cl[3];
-    float u[3];
+// the patch cell that holds cell-local x (clamped to the 3x3x3 cells of the patch), as a code
+// (cx+1) + 3 (cy+1) + 9 (cz+1), and x's coordinates in it
+__device__ __forceinline__ int patch_cell(const float x[3], int cl[3], float u[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         int f = (int)floorf(x[a]);
@@ -171,13 +168,22 @@ __device__ __forceinline__ void tri_eval(const Geo &g, int i, int j, int k, cons
         cl[a] = f;
         u[a] = x[a] - (float)f;
     }
-    float2 c[8];
+    return (cl[0] + 1) + 3 * (cl[1] + 1) + 9 * (cl[2] + 1);
+}
+
+// the 8 corners of patch cell cl of the cell at node (i, j, k), read from the field
+__device__ __forceinline__ void cell_corners(const Geo &g, int i, int j, int k, const int cl[3], float2 c[8]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int ii = wrapc(i + cl[0] + (q & 1), g.nx, g.px), jj = wrapc(j + cl[1] + ((q >> 1) & 1), g.ny, g.py);
         const int kk = wrapc(k + cl[2] + (q >> 2), g.nz, g.pz);
         c[q] = g.psi[(uint64_t)ii + (uint64_t)g.nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk)];
     }
+}
+
+// trilinear psi and its gradient (cell units) at local coordinates u of a cell with corners c, FP32
+__device__ __forceinline__ void tri_corners(const float2 c[8], const float u[3], float &vr, float &vi, float gr[3],
+                                            float gi[3]) {
     const float ux = u[0], uy = u[1], uz = u[2], mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
     const float2 a00 = make_float2(mx * c[0].x + ux * c[1].x, mx * c[0].y + ux * c[1].y);
     const float2 a10 = make_float2(mx * c[2].x + ux * c[3].x, mx * c[2].y + ux * c[3].y);
@@ -204,11 +210,19 @@ __device__ __forceinline__ bool in_patch(const float x[3]) {
 // The surrogate's final step (the refinement's Newton polish, Sec. 3.3.3 reading): the network's
 // point xs projected onto the plane through x0 normal to t = grad Re psi x grad Im psi at x0, then
 // one Newton step on (Re psi, Im psi) in that plane. False where the plain refinement must run:
-// degenerate t, singular Jacobian, or a point outside the patch.
+// degenerate t, singular Jacobian, or a point outside the patch. The corners of x0's cell and of
+// xs's cell are read together: the projected point and the Newton point mostly lie in one of the
+// two, so that the three evaluations usually wait for one round of loads instead of three.
 __device__ bool polish(const Geo &g, int i, int j, int k, const float x0[3], const float xs[3], float out[3],
                        float &rho) {
+    int c0[3], cs[3], cp[3];
+    float u0[3], us[3], up[3];
+    const int k0 = patch_cell(x0, c0, u0), ks = patch_cell(xs, cs, us);
+    float2 A[8], B[8], C[8];
+    cell_corners(g, i, j, k, c0, A);
+    cell_corners(g, i, j, k, cs, B);
     float vr, vi, gr[3], gi[3];
-    tri_eval(g, i, j, k, x0, vr, vi, gr, gi);
+    tri_corners(A, u0, vr, vi, gr, gi);
     float t[3] = {gr[1] * gi[2] - gr[2] * gi[1], gr[2] * gi[0] - gr[0] * gi[2], gr[0] * gi[1] - gr[1] * gi[0]};
     const float tn = sqrtf(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     const float nr = sqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
@@ -232,7 +246,14 @@ __device__ bool polish(const Geo &g, int i, int j, int k, const float x0[3], con
 #pragma unroll
     for (int a = 0; a < 3; ++a) xp[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
     if (!in_patch(xp)) return false;
-    tri_eval(g, i, j, k, xp, vr, vi, gr, gi);
+    const int kp = patch_cell(xp, cp, up);
+    if (kp == ks || kp == k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) C[q] = kp == ks ? B[q] : A[q];
+    } else {
+        cell_corners(g, i, j, k, cp, C);
+    }
+    tri_corners(C, up, vr, vi, gr, gi);
     const float j00 = e1[0] * gr[0] + e1[1] * gr[1] + e1[2] * gr[2], j01 = e2[0] * gr[0] + e2[1] * gr[1] + e2[2] * gr[2];
     const float j10 = e1[0] * gi[0] + e1[1] * gi[1] + e1[2] * gi[2], j11 = e2[0] * gi[0] + e2[1] * gi[1] + e2[2] * gi[2];
     const float det = j00 * j11 - j01 * j10;
@@ -242,7 +263,10 @@ __device__ bool polish(const Geo &g, int i, int j, int k, const float x0[3], con
 #pragma unroll
     for (int a = 0; a < 3; ++a) out[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
     if (!in_patch(out)) return false;
-    tri_eval(g, i, j, k, out, vr, vi, gr, gi);
+    int co[3];
+    float uo[3];
+    if (patch_cell(out, co, uo) != kp) cell_corners(g, i, j, k, co, C);
+    tri_corners(C, uo, vr, vi, gr, gi);
     rho = vr * vr + vi * vi;
     return true;
 }

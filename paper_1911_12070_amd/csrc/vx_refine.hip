@@ -657,7 +657,10 @@ __device__ __forceinline__ float halve_n(float a, int n) {  // n multiplications
 }
 
 __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t run_limit) {
+    // the 4x4x4 node patch of each group's sample, node (a, b, c) at a + 4 b + 16 c (offsets -1 .. 2)
+    __shared__ float2 s_patch[REF_THREADS / SPEC_G][64];
     const int tid = threadIdx.x, lane = tid & 63, h = lane & (SPEC_G - 1), gl = lane - h;
+    float2 *patch = s_patch[tid / SPEC_G];
     if (blockIdx.x == 0 && tid == 0) *A.chunks = 0ull;  // chunk counter of the refine_k launch that follows
     const int64_t n = min(*A.count, A.cap);
     if (n > run_limit) return;  // a long list, refined by refine_k (uniform)
@@ -684,6 +687,17 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         const int gj = (int)divmod53(rxy, nx64, rnx, ri);
         const int gi = (int)ri;
         const Box box = patch_box(gi, gj, gk, A.nx, A.ny, A.nz, A.px, A.py, A.pz);
+        // the whole patch at once (lane h: row h, x offsets -1 .. 2), so that a cell change costs an
+        // LDS read instead of a round trip to memory; the nodes are those fetch_corners would read
+        {
+            const uint32_t jj = wrap(gj, (h & 3) - 1, A.ny, A.py), kk = wrap(gk, (h >> 2) - 1, A.nz, A.pz);
+            const float2 *row = A.psi + nx64 * jj + nxy * kk;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) patch[4 * h + a] = row[wrap(gi, a - 1, A.nx, A.px)];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         uint32_t status = 0;
         V3 x0 = first_estimate(desc, status);
         if (A.seed) x0 = v3(A.seed[3 * s], A.seed[3 * s + 1], A.seed[3 * s + 2]);
@@ -695,8 +709,10 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             const int code = locate(xt, box, c, u);
             if (code != ccode) {
                 ccode = code;
+                const int base = (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
                 float2 w[8];
-                fetch_corners(A.psi, A.nx, A.ny, A.nz, A.px, A.py, A.pz, gi, gj, gk, c, w);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) w[d] = patch[base + (d & 1) + 4 * ((d >> 1) & 1) + 16 * (d >> 2)];
                 tri_coeffs(w, cw);
             }
             trilinear(cw, u, tr, ti, tgr, tgi);
