@@ -736,7 +736,8 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // the second layer, straight into a B operand of the head, whose k index is permuted to match
 // (k = 8q + j holds feature 32w + 4q + j for j < 4 and 32w + 16 + 4q + j - 4 otherwise, q = lane / 16).
 // Each wavefront thus multiplies its own 32 features by the matching rows of W3 and the eight
-// partial heads of a cell are summed in LDS: three barriers per tile (features, first layer, head).
+// partial heads of a cell are summed in LDS, by wavefront 0 after the next tile's first barrier: two
+// barriers per tile (features, first layer).
 // The barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell
 // ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
@@ -794,6 +795,21 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
             for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
         }
     };
+    // output of tile tt (if it is one of this workgroup's tiles): bias + the eight partial heads
+    auto head_out = [&](int64_t tt) {
+        if (tt >= (int64_t)blockIdx.x && t < TM && tt * TM + t < n) {
+            float4 o = bias3;
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                const float4 p = *(const float4 *)(sP + (u * TM + t) * NOUT);
+                o.x += p.x;
+                o.y += p.y;
+                o.z += p.z;
+                o.w += p.w;
+            }
+            net_out[tt * TM + t] = make_float4(o.x, o.y, o.z, 1.f / (1.f + expf(-o.w)));
+        }
+    };
     int64_t tile = blockIdx.x;
     fetch(cell_of(tile));
     uint64_t cell_next = cell_of(tile + G);
@@ -815,6 +831,9 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
         fetch(cell_next);
         cell_next = cell_of(tile + 2 * G);
         lds_barrier();  // sX complete (and, at the first tile, the table and the biases)
+        // the previous tile's partial heads were complete at this barrier; wavefront 0 sums them
+        // (they are overwritten only after the next barrier, which it reaches after reading them)
+        head_out(tile - G);
         // this lane accumulates features n0 + 16c + q4 + 0..3 of cell 16rr + l % 16, from their biases
         f32x4 acc[4][2];
 #pragma unroll
@@ -833,7 +852,7 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 #pragma unroll
                 for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b1[c][kk], a[rr], acc[rr][c]);
         }
-        // sH is free: the previous tile's second layer ended before its last barrier
+        // sH is free: the previous tile's second layer ended before this tile's first barrier
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -869,20 +888,9 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
             const f32x4 z = mfma(a3, __builtin_bit_cast(bf16x8, hv), f32x4{0.f, 0.f, 0.f, 0.f});
             if (l < 16) *(f32x4 *)(sP + (w * TM + 16 * rr + l) * NOUT) = z;
         }
-        lds_barrier();  // partial heads complete
-        if (t < TM && tile * TM + t < n) {
-            float4 o = bias3;
-#pragma unroll
-            for (int u = 0; u < NW; ++u) {
-                const float4 p = *(const float4 *)(sP + (u * TM + t) * NOUT);
-                o.x += p.x;
-                o.y += p.y;
-                o.z += p.z;
-                o.w += p.w;
-            }
-            net_out[tile * TM + t] = make_float4(o.x, o.y, o.z, 1.f / (1.f + expf(-o.w)));
-        }
     }
+    lds_barrier();  // the last tile's partial heads complete
+    head_out(tile - G);
 }
 
 // Inference, part 2: one thread per listed cell. Confident single-core interior cells get the
