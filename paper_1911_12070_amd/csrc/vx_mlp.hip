@@ -210,17 +210,36 @@ __device__ __forceinline__ bool in_patch(const float x[3]) {
 // The surrogate's final step (the refinement's Newton polish, Sec. 3.3.3 reading): the network's
 // point xs projected onto the plane through x0 normal to t = grad Re psi x grad Im psi at x0, then
 // one Newton step on (Re psi, Im psi) in that plane. False where the plain refinement must run:
-// degenerate t, singular Jacobian, or a point outside the patch. The corners of x0's cell and of
-// xs's cell are read together: the projected point and the Newton point mostly lie in one of the
-// two, so that the three evaluations usually wait for one round of loads instead of three.
-__device__ bool polish(const Geo &g, int i, int j, int k, const float x0[3], const float xs[3], float out[3],
-                       float &rho) {
+// degenerate t, singular Jacobian, or a point outside the patch. The corners of the cell itself
+// (patch cell code 13) come from ctr, 64 contiguous bytes written by the network kernel, the others
+// from the field; those of x0's cell and of xs's cell are read together: the projected point and
+// the Newton point mostly lie in one of the two, so that the three evaluations usually wait for one
+// round of loads instead of three.
+__device__ bool polish(const Geo &g, int i, int j, int k, const float4 *ctr, const float x0[3], const float xs[3],
+                       float out[3], float &rho) {
+    constexpr int CENTRE = 13;
     int c0[3], cs[3], cp[3];
     float u0[3], us[3], up[3];
     const int k0 = patch_cell(x0, c0, u0), ks = patch_cell(xs, cs, us);
-    float2 A[8], B[8], C[8];
-    cell_corners(g, i, j, k, c0, A);
-    cell_corners(g, i, j, k, cs, B);
+    float2 A[8], B[8], C[8], Z[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 e = ctr[q];
+        Z[2 * q] = make_float2(e.x, e.y);
+        Z[2 * q + 1] = make_float2(e.z, e.w);
+    }
+    if (k0 == CENTRE) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) A[q] = Z[q];
+    } else {
+        cell_corners(g, i, j, k, c0, A);
+    }
+    if (ks == CENTRE) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) B[q] = Z[q];
+    } else {
+        cell_corners(g, i, j, k, cs, B);
+    }
     float vr, vi, gr[3], gi[3];
     tri_corners(A, u0, vr, vi, gr, gi);
     float t[3] = {gr[1] * gi[2] - gr[2] * gi[1], gr[2] * gi[0] - gr[0] * gi[2], gr[0] * gi[1] - gr[1] * gi[0]};
@@ -742,7 +761,7 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
                                                    const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
-                                                   int64_t *fb_count) {
+                                                   float4 *centre, int64_t *fb_count) {
     constexpr int NW = NTI / 64;
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
@@ -826,6 +845,15 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
             uint32_t *dst = (uint32_t *)(sX + r * XP + 32 * pc + 16 * hb);
 #pragma unroll
             for (int q = 0; q < 8; ++q) dst[q] = pack2(v[q].x * is, v[q].y * is);
+            // the cell's own corners d = dx + 2 dy + 4 dz (nodes 1, 2 of rows 1, 2 of planes 1, 2) for
+            // the polish: row 1 is this thread's second row if hb = 0, row 2 its first if hb = 1
+            // (streaming stores: read once, by the next kernel)
+            const int64_t s = tile * TM + r;
+            if ((pc == 1 || pc == 2) && s < n) {
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                const float2 c0 = hb ? v[1] : v[5], c1 = hb ? v[2] : v[6];
+                __builtin_nontemporal_store((f4v){c0.x, c0.y, c1.x, c1.y}, (f4v *)(centre + 4 * s + hb + 2 * (pc - 1)));
+            }
         }
         // next tile's nodes and the ids of the one after, in flight while this tile's layers run
         fetch(cell_next);
@@ -898,8 +926,9 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 // (cell, descriptor, position in the list) for the plain refinement, with one atomic per wavefront.
 __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict__ cells,
                                                const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
-                                               int64_t cap, const float4 *__restrict__ net_out, float thr,
-                                               vx_sample *out, uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
+                                               int64_t cap, const float4 *__restrict__ net_out,
+                                               const float4 *__restrict__ centre, float thr, vx_sample *out,
+                                               uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
                                                int64_t *fb_count) {
     const int64_t n = min(*count, cap);
     if ((int64_t)blockIdx.x * NT >= n) return;  // uniform per workgroup
@@ -924,7 +953,7 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
             const float x0v[3] = {x0, y0, z0};
             const float xs[3] = {x0 + o.x, y0 + o.y, z0 + o.z};
             float x[3], rho = 0.f;
-            mine = polish(g, i, j, k, x0v, xs, x, rho);
+            mine = polish(g, i, j, k, centre + 4 * s, x0v, xs, x, rho);
             if (mine) {
                 vx_sample r{};
                 r.cell = cell;
@@ -972,6 +1001,7 @@ struct vx_mlp {
     // inference fallback queue (grown on demand)
     int64_t fb_cap = 0;
     float4 *net_out = nullptr;
+    float4 *centre = nullptr;  // [cap][4]: the 8 corners of each listed cell, for the polish
     uint64_t *fb_cell = nullptr;
     uint16_t *fb_desc = nullptr;
     int64_t *fb_index = nullptr;
@@ -1249,7 +1279,8 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     if (vx_status st = vx_check_refine_params(h, prm)) return st;
     if (vx_status st = vx_bind(h)) return st;
     if (cap > m->fb_cap) {  // fallback queue sized for the whole list
-        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index, (void *)m->net_out}) {
+        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index, (void *)m->net_out,
+                        (void *)m->centre}) {
             if (!q) continue;
             (void)hipFree(q);
             for (auto &a : m->allocs)
@@ -1259,9 +1290,11 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
         m->fb_desc = nullptr;
         m->fb_index = nullptr;
         m->net_out = nullptr;
+        m->centre = nullptr;
         m->fb_cap = 0;
         vx_status st = dalloc(m, (void **)&m->fb_cell, (size_t)cap * 8);
         if (st == VX_OK) st = dalloc(m, (void **)&m->net_out, (size_t)cap * sizeof(float4));
+        if (st == VX_OK) st = dalloc(m, (void **)&m->centre, (size_t)cap * 4 * sizeof(float4));
         if (st == VX_OK) st = dalloc(m, (void **)&m->fb_desc, (size_t)cap * 2);
         if (st == VX_OK) st = dalloc(m, (void **)&m->fb_index, (size_t)cap * 8);
         if (st) return st;
@@ -1273,11 +1306,12 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     const int64_t tiles = (cap + TM - 1) / TM;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu));
     hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
-                       d_count, cap, m->net_out, m->fb_count);
+                       d_count, cap, m->net_out, m->centre, m->fb_count);
     tm.stop();
     vx_timer tp(h, hs, VX_KIND_POLISH);
     hipLaunchKernelGGL(polish_k, dim3((unsigned)((cap + NT - 1) / NT)), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
-                       d_cell_desc, d_count, cap, (const float4 *)m->net_out, conf_threshold, d_out, m->fb_cell,
+                       d_cell_desc, d_count, cap, (const float4 *)m->net_out, (const float4 *)m->centre, conf_threshold,
+                       d_out, m->fb_cell,
                        m->fb_desc, m->fb_index, m->fb_count);
     tp.stop();
     vx_status st = vx_hip_check(h, hipGetLastError(), "surrogate inference launch");
