@@ -646,13 +646,17 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
 // one pass; the points outside the patch before it set VX_SAMPLE_BOUNDARY as they would have one at
 // a time. Every lane of a group holds the sample's state. The arithmetic is refine_k's: the shared
 // functions above, the same expressions for the trial point and the acceptance tests, and halvings
-// as the same sequence of exact multiplications by 1/2, so the samples are bit-identical to refine_k's.
+// equal to the same sequence of exact multiplications by 1/2, so the samples are bit-identical to
+// refine_k's.
 // A lane keeps the interpolation coefficients of the cell of its last evaluation in registers.
 constexpr int SPEC_G = 16;
 
 __device__ __forceinline__ float halve_n(float a, int n) {  // n multiplications by 0.5f, n in [0, SPEC_G]
-#pragma unroll
-    for (int j = 0; j < SPEC_G; ++j) a = j < n ? 0.5f * a : a;
+    // each halving of a normal number is exact, so n of them are one exponent change, as long as the
+    // result stays normal (a >= 2^-100 covers n <= SPEC_G with room); below that, one at a time
+    if (fabsf(a) >= 0x1p-100f) return __builtin_ldexpf(a, -n);
+#pragma unroll 1
+    for (int j = 0; j < n; ++j) a = 0.5f * a;
     return a;
 }
 
