@@ -22,6 +22,7 @@ struct vx_event_pair {
 struct vx_handle {
     int device = 0;
     int num_cu = 0;
+    int lds_per_cu = 0;  // bytes of LDS per CU
     std::string err;
     bool profile = false;
     std::vector<vx_event_pair> events;  // recorded pairs (pool grows as needed)
@@ -31,6 +32,7 @@ struct vx_handle {
     int ref_blocks_per_cu = 0;   // resident refinement workgroups per CU (0 = not yet queried)
     int refb_blocks_per_cu = 0;  // the same for the batched refinement kernel
     int refs_blocks_per_cu = 0;  // the same for the short-list refinement kernel
+    int wind_lds_pad = -1;       // dynamic LDS bytes per winding workgroup (-1 = not yet computed)
     int ref_refill = 8;          // idle lanes a refinement wavefront waits for before claiming samples
     unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter
     std::map<std::array<int, 4>, int> tuned_zc;  // (nx, ny, nz, periodic) -> planes per z-chunk

@@ -62,6 +62,7 @@ extern "C" vx_status vx_create(int device, vx_handle **out) {
         return VX_ERR_DEVICE;
     }
     h->num_cu = prop.multiProcessorCount;
+    h->lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
     if (hipMalloc((void **)&h->d_work, 256) != hipSuccess) {
         delete h;
         return VX_ERR_NOMEM;
