@@ -772,10 +772,8 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             const bool valid = hv + h < P.max_halvings;
             const bool inside = valid && in_patch(xt, box);
             const bool stuck = inside && mode == MODE_NEWTON && ty1 == y1 && ty2 == y2;
-            tr = 0.f;
-            ti = 0.f;
-            tgr = v3(0.f, 0.f, 0.f);
-            tgi = tgr;
+            // a lane that does not evaluate keeps stale values, which are never taken: only an
+            // accepting lane's are broadcast
             if (inside && !stuck) eval(xt, tr, ti, tgr, tgi);
             const float ft = tr * tr + ti * ti;
             const bool descent = mode == MODE_DESCENT;
