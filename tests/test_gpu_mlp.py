@@ -248,3 +248,52 @@ def test_infer_fallback_and_surrogate(ex, tmp_path):
     assert np.array_equal(vx_mlp_get_params(ex.h, m2), vx_mlp_get_params(ex.h, m))
     vx_mlp_destroy(ex.h, m)
     vx_mlp_destroy(ex.h, m2)
+
+
+def test_infer_edge_cases(ex):
+    """Empty list, capacity below the count, out-of-range ids and an open (non-periodic) grid. The
+    inference writes exactly the first min(count, cap) samples; with threshold 0 every sample it
+    cannot serve (cells at the open boundary, bad ids, cells without exactly two pierced faces) is the
+    plain refinement's, bit for bit, and bad ids carry VX_SAMPLE_BAD_CELL."""
+    import torch
+    from paper_1911_12070_amd import (SAMPLE_BAD_CELL, SAMPLE_SURROGATE, dims, samples_to_numpy, vx_mlp_destroy,
+                                      vx_mlp_infer)
+    psi_np, psi, out = field_cells(ex, seed=24, shape=(40, 36, 32), periodic=0)
+    nc = int(out["counts"][1])
+    nz, ny, nx = psi_np.shape
+    d = dims(nx, ny, nz, 0)
+    assert nc > 100
+    cells = out["cells"].clone()
+    bad = [0, nc // 2, nc - 1]
+    cells[bad] = nx * ny * nz + 5
+    wout = {"cells": cells[:nc], "cdesc": out["cdesc"][:nc], "counts": out["counts"]}
+    plain = samples_to_numpy(ex.refine(psi, wout, 0), nc)
+    m = make_mlp(ex, vxinputs.mlp_init(15))
+    count = out["counts"][1:]
+
+    def infer(cnt, cap):
+        res = torch.full((nc, 8), -7, dtype=torch.int32, device="cuda")
+        vx_mlp_infer(ex.h, m, d, psi, cells, out["cdesc"], cnt, cap, 0.0, res)
+        torch.cuda.synchronize()
+        return res
+
+    full = infer(count, nc)
+    b = samples_to_numpy(full, nc)
+    sur = (b["status"] & SAMPLE_SURROGATE) != 0
+    log(f"open grid: {sur.sum()} of {nc} cells from the surrogate")
+    assert sur.any() and not sur.all()
+    assert b[~sur].tobytes() == plain[~sur].tobytes()
+    assert ((b["status"][bad] & SAMPLE_BAD_CELL) != 0).all()
+    # no surrogate sample at the open boundary (the network's patch would leave the grid)
+    cid = b["cell"][sur].astype(np.int64)
+    i, j, k = cid % nx, (cid // nx) % ny, cid // (nx * ny)
+    assert ((i >= 1) & (i + 2 < nx) & (j >= 1) & (j + 2 < ny) & (k >= 1) & (k + 2 < nz)).all()
+    # empty list: nothing written
+    empty = infer(torch.zeros(1, dtype=torch.int64, device="cuda"), nc)
+    assert (empty == -7).all()
+    # capacity below the count: the first cap samples, as in the full call, and nothing beyond
+    cap = nc // 3
+    part = infer(count, cap)
+    assert torch.equal(part[:cap], full[:cap])
+    assert (part[cap:] == -7).all()
+    vx_mlp_destroy(ex.h, m)
