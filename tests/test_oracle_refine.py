@@ -208,3 +208,87 @@ def test_bruteforce_nearest_zero():
         agree += np.linalg.norm(nearest - x) < 1e-6
     assert total > 60
     assert agree / total > 0.95, (agree, total)
+
+
+# ---------------------------------------------------------------- tangent fallback (Sec. 3.3.3)
+# The pseudo-vorticity grad Re psi x grad Im psi gives the line direction wherever it is not
+# degenerate. The cases below are fields built from node values whose trilinear interpolation is
+# the stated polynomial exactly (only products of distinct coordinates appear), chosen so that the
+# pseudo-vorticity vanishes at x0 while the cell is pierced: the refinement then has to use the
+# cell's face flux, or the first pierced face's normal when the flux cancels.
+
+def _plain_trilerp(re, im, x):
+    """Trilinear value of a 4x4x4 patch at x (independent of the oracle's evaluation)."""
+    c = np.clip(np.floor(x), -1, 1).astype(int)
+    u = x - c
+    v = 0j
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = (u[0] if dx else 1 - u[0]) * (u[1] if dy else 1 - u[1]) * (u[2] if dz else 1 - u[2])
+                q = (c[2] + 1 + dz, c[1] + 1 + dy, c[0] + 1 + dx)
+                v += w * (re[q] + 1j * im[q])
+    return v
+
+
+def _faces_of(desc):
+    out = []
+    for f in range(6):
+        v = (desc >> (2 * f)) & 3
+        out.append(1 if v == 1 else (-1 if v == 3 else 0))
+    return out
+
+
+@pytest.mark.parametrize("px", [0.3125, 0.71875, 0.1])
+def test_tangent_fallback_face_flux_plane(px):
+    # Re psi = x - px, Im psi = (3/4)(x - 1/2)(y - 1/2): a straight core along z at (px, 1/2);
+    # grad Im psi = 0 at the cell centre, so grad Re x grad Im = 0 there
+    re, im = patch_from_function(lambda x, y, z: (x - px) + 0.75j * (x - 0.5) * (y - 0.5) + 0 * z)
+    d = desc_of_patch(re, im)
+    f6 = _faces_of(d)
+    assert f6[:4] == [0, 0, 0, 0] and f6[4] == f6[5] != 0  # pierced through -z and +z only
+    x0 = x0_of_desc(d)
+    assert np.array_equal(x0, [0.5, 0.5, 0.5])
+    _, g = oracle.trilerp(re, im, x0)
+    assert np.linalg.norm(np.cross(g.real, g.imag)) == 0.0
+    x, rho, it, st = oracle.refine_patch(re, im, d)
+    assert st & oracle.TANGENT_FALLBACK
+    assert not st & (oracle.NONZERO_MIN | oracle.NOT_CONVERGED)
+    # face flux (w_z(n) + w_z(n+ez)) e_z: the plane z = 1/2, whose only zero is (px, 1/2, 1/2)
+    assert it > 0 and abs(x[2] - 0.5) < 1e-15
+    assert np.abs(x - [px, 0.5, 0.5]).max() < 1e-12
+    assert rho < 1e-24 and abs(_plain_trilerp(re, im, x)) < 1e-12
+
+
+@pytest.mark.parametrize("eta,fallback", [(1e-9, True), (1e-7, True), (1e-5, False), (1e-3, False)])
+def test_tangent_fallback_threshold(eta, fallback):
+    # grad Re = (1, 0, 0), grad Im = (1/2, eta, 0) at the centre: |t| = eta against
+    # 1e-6 |grad Re| |grad Im| = 5e-7; both planes are z = 1/2, with the zero at (5/16, 1/2, 1/2)
+    px = 0.3125
+    re, im = patch_from_function(lambda x, y, z: (x - px) + 1j * (
+        0.5 * (x - px) + 0.75 * (x - 0.5) * (y - 0.5) + eta * (y - 0.5)) + 0 * z)
+    d = desc_of_patch(re, im)
+    x, rho, it, st = oracle.refine_patch(re, im, d)
+    assert bool(st & oracle.TANGENT_FALLBACK) == fallback
+    assert np.abs(x - [px, 0.5, 0.5]).max() < 1e-12
+
+
+@pytest.mark.parametrize("y1,gam,kap", [(0.55, 0.25, 2 ** -5), (0.45, 0.25, -2 ** -5), (0.5625, -0.5, 2 ** -4)])
+def test_tangent_fallback_first_face_normal(y1, gam, kap):
+    # Re psi = y - y1, Im psi = (x - 1/2)(z - 1/2) - kap + gam (y - 1/2): the zero set is a
+    # hyperbola in the plane y = y1 that crosses the faces -x, +x, -z, +z; the x and z fluxes
+    # cancel, grad Re || grad Im at the centre. The direction is then the first pierced face's
+    # normal (-x): the plane x = 1/2, on which |psi|^2 depends on y alone and has no zero.
+    re, im = patch_from_function(lambda x, y, z: (y - y1) + 1j * ((x - 0.5) * (z - 0.5) - kap + gam * (y - 0.5)))
+    d = desc_of_patch(re, im)
+    f6 = _faces_of(d)
+    assert f6[0] != 0 and f6[1] != 0 and f6[4] != 0 and f6[5] != 0 and f6[2] == f6[3] == 0
+    assert f6[0] + f6[1] == 0 and f6[4] + f6[5] == 0  # zero face flux on every axis
+    x, rho, it, st = oracle.refine_patch(re, im, d)
+    assert st & oracle.TANGENT_FALLBACK and st & oracle.MULTI and st & oracle.NONZERO_MIN
+    assert x[0] == 0.5 and x[2] == 0.5  # stays in the plane x = 1/2 and on the line of steepest descent
+    y_min = (y1 + gam * (kap + 0.5 * gam)) / (1 + gam * gam)  # minimiser of (y-y1)^2 + (gam(y-1/2)-kap)^2
+    assert abs(x[1] - y_min) < 0.01
+    ys = np.linspace(-1, 2, 3001)
+    f_plane = [abs(_plain_trilerp(re, im, np.array([0.5, yy, 0.5]))) ** 2 for yy in ys]
+    assert rho <= min(f_plane) + 1e-5

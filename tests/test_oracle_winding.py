@@ -263,3 +263,70 @@ def test_ring_closed_cycle_and_sign():
             r = fc[:2] - np.array([cx, cy])
             ephi = np.array([-r[1], r[0], 0.0]) / np.linalg.norm(r)
             assert np.sign(ephi[a]) == -w
+
+
+# ------------------------------------------------------------------ box evaluation = whole-grid pass
+def _box_sub(psi, origin, size, periodic, rng):
+    """Values of the box plus one node in each positive direction, wrapped on periodic axes;
+    nodes past the end of an open axis get random values (they must never be read)."""
+    nz, ny, nx = psi.shape
+    x0, y0, z0 = origin
+    bx, by, bz = size
+    out = np.empty((bz + 1, by + 1, bx + 1), np.complex64)
+    for k in range(bz + 1):
+        for j in range(by + 1):
+            for i in range(bx + 1):
+                g = [x0 + i, y0 + j, z0 + k]
+                outside = False
+                for a, n in enumerate((nx, ny, nz)):
+                    if g[a] >= n:
+                        if (periodic >> a) & 1:
+                            g[a] %= n
+                        else:
+                            outside = True
+                if outside:
+                    out[k, j, i] = complex(*rng.standard_normal(2))
+                else:
+                    out[k, j, i] = psi[g[2], g[1], g[0]]
+    return out
+
+
+def _small_int_field(rng, shape):
+    vals = rng.integers(-2, 3, size=shape + (2,)).astype(np.float32)
+    return (vals[..., 0] + 1j * vals[..., 1]).astype(np.complex64)
+
+
+@pytest.mark.parametrize("periodic", range(8))
+def test_winding_box_equals_whole_grid(periodic):
+    """The box evaluation used by sampled checks of large grids gives, node for node, the face
+    windings, packed bytes and cell descriptors of the whole-grid pass: whole grids, boxes inside,
+    boxes that wrap the seams of periodic axes, for every combination of periodic axes, on
+    small-integer fields (zeros and collinear values) and on smooth tangles."""
+    rng = np.random.default_rng(100 + periodic)
+    fields = [_small_int_field(rng, (5, 4, 6)), _small_int_field(rng, (3, 7, 2)),
+              vxinputs.eval_tangle(vxinputs.make_tangle((12, 10, 9), 24, (1, 3), seed=7 + periodic))]
+    for psi in fields:
+        nz, ny, nx = psi.shape
+        W = oracle.winding(psi, periodic)
+        cdesc_full = np.zeros(psi.shape, np.uint16)
+        cz, cy, cx = np.unravel_index(W.cells.astype(np.int64), psi.shape)
+        cdesc_full[cz, cy, cx] = W.cdesc
+        boxes = [((0, 0, 0), (nx, ny, nz))]
+        for _ in range(4):
+            size = tuple(int(rng.integers(1, n + 1)) for n in (nx, ny, nz))
+            origin = []
+            for a, (n, s) in enumerate(zip((nx, ny, nz), size)):
+                hi = n - 1 if (periodic >> a) & 1 else n - s  # periodic boxes may run past the seam
+                origin.append(int(rng.integers(0, hi + 1)))
+            boxes.append((tuple(origin), size))
+        for origin, size in boxes:
+            sub = _box_sub(psi, origin, size, periodic, rng)
+            w, packed, cdesc = oracle.winding_box(sub, (nx, ny, nz), origin, periodic)
+            bx, by, bz = size
+            zi = (origin[2] + np.arange(bz)) % nz
+            yi = (origin[1] + np.arange(by)) % ny
+            xi = (origin[0] + np.arange(bx)) % nx
+            sel = np.ix_(zi, yi, xi)
+            assert np.array_equal(packed, W.packed[sel]), (periodic, origin, size)
+            assert np.array_equal(w, W.w[sel]), (periodic, origin, size)
+            assert np.array_equal(cdesc, cdesc_full[sel]), (periodic, origin, size)
