@@ -269,7 +269,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["tangle_1024", "series_64"], default="tangle_1024")
     ap.add_argument("--grid", type=int, default=1024)
-    ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -302,7 +301,7 @@ def main():
         tangle = vxinputs.make_tangle((N, N, N), 4096, (8, 24), 3)
         wl = f"tangle_{N}"
     ex = Extractor(0)
-    ex.config(args.rows_per_wave, args.zchunk)
+    ex.config(args.zchunk)
     print(f"[bench] generating {N}^3 field on the GPU", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     psi = ex.gen_tangle(tangle)

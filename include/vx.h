@@ -32,9 +32,10 @@
  * Memory and streams
  *   Every buffer argument named d_* is device memory owned by the caller. The library owns only
  *   its handle and the handle's small internal state; vx_destroy frees them. All compute calls
- *   are asynchronous on the given stream (NULL = the device's null stream). Argument errors are
- *   detected on the host before anything is launched. A handle belongs to one device and must
- *   not be used by two threads at once.
+ *   are asynchronous on the given stream (NULL = the device's null stream) and allocate nothing;
+ *   the set-up calls (vx_create, vx_batch_create, vx_mlp_create, vx_mlp_reserve, the autotuners)
+ *   allocate and synchronise. Argument errors are detected on the host before anything is
+ *   launched. A handle belongs to one device and must not be used by two threads at once.
  *
  * Errors
  *   Every call returns vx_status. Nothing throws, exits or prints. vx_last_error() gives the
@@ -66,6 +67,15 @@ typedef struct {
     int32_t nx, ny, nz;
     uint32_t periodic; /* bit 0: x, bit 1: y, bit 2: z */
 } vx_dims;
+
+/* Capacity status of the work enqueued so far on this handle. Synchronises stream s (the caller
+ * synchronises any other stream it used), then returns VX_ERR_CAPACITY if any call since the last
+ * vx_sync_status found a list longer than its capacity -- pierced faces or cells beyond face_cap /
+ * cell_cap (vx_winding, batches), listed cells beyond the sample capacity (vx_refine, vx_mlp_infer,
+ * batches), training rows beyond n_cap (vx_mlp_dataset) -- with the detail in vx_last_error, and
+ * clears the flag; VX_OK otherwise. The flag is a device word of the handle that those kernels set
+ * (sticky: it is never cleared by the compute calls themselves); it travels with captured graphs. */
+vx_status vx_sync_status(vx_handle *h, vx_stream s);
 
 /* Library version (major*10000 + minor*100 + patch). */
 int vx_version(void);
@@ -121,7 +131,8 @@ vx_status vx_gen_line_ring(vx_handle *h, vx_dims dims, const vx_line_ring *p, co
  *   d_counts     int64[2]: true number of pierced faces, cells. Written even on overflow; only
  *                the first *_cap entries are stored. The call zeroes d_counts first.
  * Lists are sets: their order is unspecified and may differ between runs. Sort to compare.
- * The caller detects overflow by comparing d_counts with the capacities after synchronising.
+ * Overflow (a true count above its capacity) sets the handle's sticky capacity flag on the device;
+ * vx_sync_status reports it as VX_ERR_CAPACITY. The counts themselves also show it.
  * d_faces/d_face_sign may be NULL when face_cap == 0 (likewise cells).
  * ---------------------------------------------------------------------------------------- */
 typedef struct {
@@ -137,9 +148,9 @@ typedef struct {
 vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_winding_out *out,
                      vx_stream s);
 
-/* Tile shape of the winding kernel on this handle: zchunk = planes marched per wavefront (0 = chosen
- * from the grid size); rows_per_wave is reserved and must be 0. Results do not depend on it. */
-vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk);
+/* Depth of the winding kernel's z-chunks on this handle: planes marched per wavefront (0 = chosen
+ * from the grid size, or by vx_autotune for that shape). Results do not depend on it. */
+vx_status vx_wind_config(vx_handle *h, int zchunk);
 
 /* ------------------------------------------------------------------------------------------
  * Core-sample refinement (Sec. 3.3.1 mean estimate, Sec. 3.3.3 density-guided minimisation).
@@ -226,6 +237,11 @@ typedef struct {
  * the training calls (their scratch, about 3 KiB per row, is allocated here). */
 vx_status vx_mlp_create(vx_handle *h, const float *h_params, int64_t max_batch, vx_mlp **out);
 vx_status vx_mlp_destroy(vx_mlp *m);
+/* Reserve the inference buffers of vx_mlp_infer for lists of up to max_cells cells (98 bytes per
+ * cell: network outputs, the cells' corners for the polish, the fallback queue). Allocating and
+ * synchronous (it waits for the device first, since earlier work may still read the old buffers);
+ * a smaller max_cells than already reserved keeps the buffers. vx_mlp_infer itself never allocates. */
+vx_status vx_mlp_reserve(vx_mlp *m, int64_t max_cells);
 /* Copy the FP32 parameters to / from host memory (synchronous). */
 vx_status vx_mlp_get_params(vx_mlp *m, float *h_params);
 vx_status vx_mlp_set_params(vx_mlp *m, const float *h_params);
@@ -263,13 +279,18 @@ vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n, float *d_
  * estimate has two pierced faces, whose patch lies inside the grid and whose conf >= conf_threshold
  * gets the network's point x0 + Z3[0..2], projected onto the refinement's plane (through x0, normal
  * to grad Re psi x grad Im psi at x0) and polished by one Newton step on (Re psi, Im psi) in that
- * plane, FP32 (status VX_SAMPLE_SURROGATE, iters 1, rho = |trilinear psi|^2 there). Every other
- * cell, and every cell whose polish fails (degenerate tangent, singular Jacobian, point outside
- * the patch), is refined by the plain method with p (NULL = defaults), exactly as vx_refine would.
- * No host synchronisation. */
+ * plane, FP32, with the refinement's own arithmetic (status VX_SAMPLE_SURROGATE, iters 1,
+ * rho = |trilinear psi|^2 there). The polished point is kept only if the Newton step that would
+ * follow it is at most max_step cells long (an estimate of its distance from the zero of psi in
+ * the plane; max_step = 0 skips this test). Every other cell, and every cell whose polish fails
+ * (degenerate tangent, singular Jacobian, point outside the patch, longer step), is refined by the
+ * plain method with p (NULL = defaults), exactly as vx_refine would.
+ * cap must not exceed the cells reserved with vx_mlp_reserve (VX_ERR_INVALID otherwise). The call
+ * allocates nothing and does not synchronise; it uses the surrogate's inference buffers, so calls
+ * on one surrogate must not overlap in time. */
 vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
                        const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
-                       const vx_refine_params *p, vx_sample *d_out, vx_stream s);
+                       float max_step, const vx_refine_params *p, vx_sample *d_out, vx_stream s);
 
 /* ------------------------------------------------------------------------------------------
  * Batching: winding + compaction and refinement of many grids of uneven size (a time series of

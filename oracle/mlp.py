@@ -79,7 +79,7 @@ def conf_targets(Z3: np.ndarray, T: np.ndarray, tol: float) -> np.ndarray:
     return (np.abs(Z3[:, :3] - T).max(axis=1) < tol).astype(np.float64)
 
 
-def loss_grad(P: dict, X: np.ndarray, T: np.ndarray, lam: float = 0.1, tol: float = 0.02, y=None):
+def loss_grad(P: dict, X: np.ndarray, T: np.ndarray, lam: float = 0.1, tol: float = 0.25, y=None):
     """Mean loss over the batch and its gradient with respect to every parameter. y (the confidence
     targets) is computed from the forward pass unless given. Returns (loss, grads, y)."""
     n = X.shape[0]
@@ -149,11 +149,26 @@ def inside(x) -> bool:
     return bool(np.all(x >= -1.0) and np.all(x <= 2.0))
 
 
-def polish(re, im, desc: int, x_start):
+def newton_step(re, im, e1, e2, x):
+    """Length of the Newton step on (Re psi, Im psi) in the plane (e1, e2) from x: |J^-1 psi(x)| with
+    J the 2x2 in-plane Jacobian (inf if J is singular). Near a simple zero it estimates |x - zero|."""
+    from . import trilerp
+    v, g = trilerp(re, im, x)
+    J = np.array([[e1 @ g.real, e2 @ g.real], [e1 @ g.imag, e2 @ g.imag]])
+    det = J[0, 0] * J[1, 1] - J[0, 1] * J[1, 0]
+    if det == 0.0:
+        return 0.0 if v == 0 else np.inf
+    dy = np.array([J[1, 1] * v.real - J[0, 1] * v.imag, -J[1, 0] * v.real + J[0, 0] * v.imag]) / det
+    return float(np.hypot(dy[0], dy[1]))
+
+
+def polish(re, im, desc: int, x_start, max_step: float = 0.0, with_step: bool = False):
     """The surrogate's final step: x_start (the network's point) projected onto the refinement's
     plane through x0, then one Newton step on (Re psi, Im psi) in that plane (the refinement's
-    polish, Sec. 3.3.3 reading). Returns (x, |psi(x)|^2), or None where the refinement must run
-    instead: degenerate tangent, singular Jacobian, or a point outside the patch."""
+    polish, Sec. 3.3.3 reading). Returns (x, |psi(x)|^2) (plus the length of the Newton step that
+    would follow, if with_step), or None where the refinement must run instead: degenerate tangent,
+    singular Jacobian, a point outside the patch, or -- max_step > 0 -- a following Newton step
+    longer than max_step cells (the estimate of the polished point's distance from the zero)."""
     from . import trilerp
     pl = _plane(re, im, desc)
     if pl is None:
@@ -175,4 +190,8 @@ def polish(re, im, desc: int, x_start):
     if not inside(x):
         return None
     v, _ = trilerp(re, im, x)
-    return x, float(abs(v) ** 2)
+    rho = float(abs(v) ** 2)
+    nxt = newton_step(re, im, e1, e2, x)
+    if max_step > 0.0 and rho != 0.0 and not nxt <= max_step:
+        return None
+    return (x, rho, nxt) if with_step else (x, rho)

@@ -28,11 +28,11 @@ SAMPLE_BAD_CELL = 64
 KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH = 0, 1, 2, 3, 4
 
 # every symbol include/vx.h declares
-EXPORTS = ["vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
+EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
-           "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
+           "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
            "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_infer",
            "vx_profile_enable", "vx_profile_read"]
 
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
         L.vx_create.restype = st
         L.vx_destroy.argtypes = [P]
         L.vx_destroy.restype = st
+        L.vx_sync_status.argtypes = [P, P]
+        L.vx_sync_status.restype = st
         L.vx_status_str.argtypes = [i]
         L.vx_status_str.restype = ctypes.c_char_p
         L.vx_last_error.argtypes = [P]
@@ -121,7 +123,7 @@ def lib() -> ctypes.CDLL:
         L.vx_gen_line_ring.restype = st
         L.vx_winding.argtypes = [P, Dims, P, ctypes.POINTER(WindingOut), P]
         L.vx_winding.restype = st
-        L.vx_wind_config.argtypes = [P, i, i]
+        L.vx_wind_config.argtypes = [P, i]
         L.vx_wind_config.restype = st
         L.vx_refine_defaults.argtypes = []
         L.vx_refine_defaults.restype = RefineParams
@@ -144,6 +146,7 @@ def lib() -> ctypes.CDLL:
         i64, f = ctypes.c_int64, ctypes.c_float
         L.vx_mlp_create.argtypes = [P, P, i64, ctypes.POINTER(P)]
         L.vx_mlp_destroy.argtypes = [P]
+        L.vx_mlp_reserve.argtypes = [P, i64]
         L.vx_mlp_get_params.argtypes = [P, P]
         L.vx_mlp_set_params.argtypes = [P, P]
         L.vx_mlp_save.argtypes = [P, ctypes.c_char_p]
@@ -153,8 +156,8 @@ def lib() -> ctypes.CDLL:
         L.vx_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.POINTER(AdamParams), P, P]
         L.vx_mlp_grad.argtypes = [P, P, P, i64, f, f, P, P, P]
         L.vx_mlp_forward.argtypes = [P, P, i64, P, P]
-        L.vx_mlp_infer.argtypes = [P, Dims, P, P, P, P, i64, f, ctypes.POINTER(RefineParams), P, P]
-        for name in ("vx_mlp_create", "vx_mlp_destroy", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save",
+        L.vx_mlp_infer.argtypes = [P, Dims, P, P, P, P, i64, f, f, ctypes.POINTER(RefineParams), P, P]
+        for name in ("vx_mlp_create", "vx_mlp_destroy", "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save",
                      "vx_mlp_load", "vx_mlp_dataset", "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad",
                      "vx_mlp_forward", "vx_mlp_infer"):
             getattr(L, name).restype = st
@@ -232,8 +235,13 @@ def vx_winding(h, d: Dims, psi, counts, wind=None, faces=None, fsign=None, cells
     _check(h, lib().vx_winding(h, d, _ptr(psi), ctypes.byref(out), _stream(stream)), "vx_winding")
 
 
-def vx_wind_config(h, rows_per_wave: int = 0, zchunk: int = 0):
-    _check(h, lib().vx_wind_config(h, int(rows_per_wave), int(zchunk)), "vx_wind_config")
+def vx_wind_config(h, zchunk: int = 0):
+    _check(h, lib().vx_wind_config(h, int(zchunk)), "vx_wind_config")
+
+
+def vx_sync_status(h, stream=None):
+    """Raises VxError(VX_ERR_CAPACITY) if a list overflowed since the last call (clears the flag)."""
+    _check(h, lib().vx_sync_status(h, _stream(stream)), "vx_sync_status")
 
 
 def vx_refine_defaults() -> RefineParams:
@@ -312,6 +320,10 @@ def vx_mlp_destroy(h, m):
     _check(h, lib().vx_mlp_destroy(m), "vx_mlp_destroy")
 
 
+def vx_mlp_reserve(h, m, max_cells: int):
+    _check(h, lib().vx_mlp_reserve(m, int(max_cells)), "vx_mlp_reserve")
+
+
 def vx_mlp_get_params(h, m):
     import numpy as np
     a = np.empty(MLP_NPARAMS, np.float32)
@@ -357,12 +369,17 @@ def vx_mlp_forward(h, m, feat, n: int, out, stream=None):
     _check(h, lib().vx_mlp_forward(m, _ptr(feat), int(n), _ptr(out), _stream(stream)), "vx_mlp_forward")
 
 
+# default acceptance bound of the surrogate's polished point: the Newton step that would follow it (an
+# estimate of its distance from the core) must be at most this many cells
+MLP_MAX_STEP = 0.02
+
+
 def vx_mlp_infer(h, m, d: Dims, psi, cells, cdesc, count, cap, conf_threshold: float, out,
-                 params: RefineParams | None = None, stream=None):
+                 params: RefineParams | None = None, stream=None, max_step: float = MLP_MAX_STEP):
     prm = params if params is not None else vx_refine_defaults()
     _check(h, lib().vx_mlp_infer(m, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(count), int(cap),
-                                 float(conf_threshold), ctypes.byref(prm), _ptr(out), _stream(stream)),
-           "vx_mlp_infer")
+                                 float(conf_threshold), float(max_step), ctypes.byref(prm), _ptr(out),
+                                 _stream(stream)), "vx_mlp_infer")
 
 
 def vx_profile_enable(h, enable: bool = True):

@@ -27,16 +27,20 @@ struct vx_handle {
     bool profile = false;
     std::vector<vx_event_pair> events;  // recorded pairs (pool grows as needed)
     size_t events_used = 0;
-    int wind_ty = 0;  // rows per wavefront of the winding kernel (0 = default)
     int wind_zc = 0;  // planes per z-chunk (0 = chosen from the grid)
     int ref_blocks_per_cu = 0;   // resident refinement workgroups per CU (0 = not yet queried)
     int refb_blocks_per_cu = 0;  // the same for the batched refinement kernel
     int refs_blocks_per_cu = 0;  // the same for the short-list refinement kernel
     int wind_lds_pad = -1;       // dynamic LDS bytes per winding workgroup (-1 = not yet computed)
     int ref_refill = 8;          // idle lanes a refinement wavefront waits for before claiming samples
-    unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter
+    unsigned long long *d_work = nullptr;  // device workspace: [0] refinement chunk counter, [1] overflow flags
     std::map<std::array<int, 4>, int> tuned_zc;  // (nx, ny, nz, periodic) -> planes per z-chunk
 };
+
+// Sticky overflow flags in the handle's workspace (device word d_work[1]): set by kernels that find
+// a list longer than its capacity, read and cleared by vx_sync_status.
+enum : unsigned { VX_OVERFLOW_WIND = 1u, VX_OVERFLOW_REFINE = 2u, VX_OVERFLOW_DATASET = 4u };
+inline unsigned long long *vx_overflow_flag(vx_handle *h) { return h->d_work + 1; }
 
 // Arguments of the winding kernel for one grid (one frame of a batch).
 struct vx_wind_args {
@@ -49,6 +53,7 @@ struct vx_wind_args {
     uint16_t *cdesc;
     int64_t ccap;
     int64_t *counts;
+    unsigned long long *flag;  // sticky overflow flags (VX_OVERFLOW_WIND set when a list overflows)
     int nx, ny, nz;
     int px, py, pz;
     int ntx, nty, ntz, zc;

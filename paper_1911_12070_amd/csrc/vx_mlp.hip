@@ -28,7 +28,7 @@
 #include <cstring>
 #include <new>
 
-#include "vx_internal.h"
+#include "vx_refine_math.h"
 
 namespace {
 
@@ -135,93 +135,26 @@ __device__ __forceinline__ void gather_features(const Geo &g, int i, int j, int 
     }
 }
 
-__device__ __forceinline__ void first_estimate(uint32_t desc, float &x, float &y, float &z, int &n) {
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    n = 0;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (((desc >> (2 * f)) & 3u) == 0) continue;
-        const int a = f >> 1;
-        const float side = (float)(f & 1);
-        sx += a == 0 ? side : 0.5f;
-        sy += a == 1 ? side : 0.5f;
-        sz += a == 2 ? side : 0.5f;
-        ++n;
-    }
-    if (n == 0) {
-        x = y = z = 0.5f;
-    } else {
-        const float inv = 1.0f / (float)n;
-        x = sx * inv;
-        y = sy * inv;
-        z = sz * inv;
-    }
-}
-
-// the patch cell that holds cell-local x (clamped to the 3x3x3 cells of the patch), as a code
-// (cx+1) + 3 (cy+1) + 9 (cz+1), and x's coordinates in it
-__device__ __forceinline__ int patch_cell(const float x[3], int cl[3], float u[3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        int f = (int)floorf(x[a]);
-        f = max(-1, min(f, 1));
-        cl[a] = f;
-        u[a] = x[a] - (float)f;
-    }
-    return (cl[0] + 1) + 3 * (cl[1] + 1) + 9 * (cl[2] + 1);
-}
-
-// the 8 corners of patch cell cl of the cell at node (i, j, k), read from the field
-__device__ __forceinline__ void cell_corners(const Geo &g, int i, int j, int k, const int cl[3], float2 c[8]) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int ii = wrapc(i + cl[0] + (q & 1), g.nx, g.px), jj = wrapc(j + cl[1] + ((q >> 1) & 1), g.ny, g.py);
-        const int kk = wrapc(k + cl[2] + (q >> 2), g.nz, g.pz);
-        c[q] = g.psi[(uint64_t)ii + (uint64_t)g.nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk)];
-    }
-}
-
-// trilinear psi and its gradient (cell units) at local coordinates u of a cell with corners c, FP32
-__device__ __forceinline__ void tri_corners(const float2 c[8], const float u[3], float &vr, float &vi, float gr[3],
-                                            float gi[3]) {
-    const float ux = u[0], uy = u[1], uz = u[2], mx = 1.f - ux, my = 1.f - uy, mz = 1.f - uz;
-    const float2 a00 = make_float2(mx * c[0].x + ux * c[1].x, mx * c[0].y + ux * c[1].y);
-    const float2 a10 = make_float2(mx * c[2].x + ux * c[3].x, mx * c[2].y + ux * c[3].y);
-    const float2 a01 = make_float2(mx * c[4].x + ux * c[5].x, mx * c[4].y + ux * c[5].y);
-    const float2 a11 = make_float2(mx * c[6].x + ux * c[7].x, mx * c[6].y + ux * c[7].y);
-    const float2 b0 = make_float2(my * a00.x + uy * a10.x, my * a00.y + uy * a10.y);
-    const float2 b1 = make_float2(my * a01.x + uy * a11.x, my * a01.y + uy * a11.y);
-    vr = mz * b0.x + uz * b1.x;
-    vi = mz * b0.y + uz * b1.y;
-    gr[2] = b1.x - b0.x;
-    gi[2] = b1.y - b0.y;
-    gr[1] = mz * (a10.x - a00.x) + uz * (a11.x - a01.x);
-    gi[1] = mz * (a10.y - a00.y) + uz * (a11.y - a01.y);
-    const float dx0 = my * (c[1].x - c[0].x) + uy * (c[3].x - c[2].x), dx1 = my * (c[5].x - c[4].x) + uy * (c[7].x - c[6].x);
-    const float dy0 = my * (c[1].y - c[0].y) + uy * (c[3].y - c[2].y), dy1 = my * (c[5].y - c[4].y) + uy * (c[7].y - c[6].y);
-    gr[0] = mz * dx0 + uz * dx1;
-    gi[0] = mz * dy0 + uz * dy1;
-}
-
-__device__ __forceinline__ bool in_patch(const float x[3]) {
-    return x[0] >= -1.f && x[0] <= 2.f && x[1] >= -1.f && x[1] <= 2.f && x[2] >= -1.f && x[2] <= 2.f;
-}
-
-// The surrogate's final step (the refinement's Newton polish, Sec. 3.3.3 reading): the network's
-// point xs projected onto the plane through x0 normal to t = grad Re psi x grad Im psi at x0, then
-// one Newton step on (Re psi, Im psi) in that plane. False where the plain refinement must run:
-// degenerate t, singular Jacobian, or a point outside the patch. The corners of the cell itself
-// (patch cell code 13) come from ctr, 64 contiguous bytes written by the network kernel, the others
-// from the field; those of x0's cell and of xs's cell are read together: the projected point and
-// the Newton point mostly lie in one of the two, so that the three evaluations usually wait for one
-// round of loads instead of three.
-__device__ bool polish(const Geo &g, int i, int j, int k, const float4 *ctr, const float x0[3], const float xs[3],
-                       float out[3], float &rho) {
-    constexpr int CENTRE = 13;
+// The surrogate's final step, in the refinement's own arithmetic (the functions of vx_refine_math.h,
+// Sec. 3.3.3 reading): the network's point xs projected onto the plane through x0 normal to
+// t = grad Re psi x grad Im psi at x0, then one Newton step on (Re psi, Im psi) in that plane.
+// False where the plain refinement must run: degenerate t, singular Jacobian, a point outside the
+// patch, or -- when max_step > 0 -- a Newton step from the polished point that would be longer than
+// max_step cells (that step estimates the polished point's distance from the zero of psi in the
+// plane, so a confident but wrong prediction goes to the plain method instead of being reported).
+// The corners of the cell itself come from ctr, 64 contiguous bytes written by the network kernel,
+// the others from the field; those of x0's cell and of xs's cell are requested together: the
+// projected point and the Newton point mostly lie in one of the two, so that the evaluations usually
+// wait for one round of loads.
+__device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const float4 *ctr, const vxr::V3 &x0,
+                       const vxr::V3 &xs, float max_step, vxr::V3 &out, float &rho) {
+    using namespace vxr;
+    constexpr int CENTRE = 21;  // locate()'s code of the cell itself: (0+1) + 4 (0+1) + 16 (0+1)
+    const Box box = patch_box(i, j, k, g.nx, g.ny, g.nz, g.px, g.py, g.pz);
     int c0[3], cs[3], cp[3];
     float u0[3], us[3], up[3];
-    const int k0 = patch_cell(x0, c0, u0), ks = patch_cell(xs, cs, us);
-    float2 A[8], B[8], C[8], Z[8];
+    const int k0 = locate(x0, box, c0, u0), ks = locate(xs, box, cs, us);
+    float2 Z[8], A[8], B[8], C[8], cf[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float4 e = ctr[q];
@@ -232,61 +165,54 @@ __device__ bool polish(const Geo &g, int i, int j, int k, const float4 *ctr, con
 #pragma unroll
         for (int q = 0; q < 8; ++q) A[q] = Z[q];
     } else {
-        cell_corners(g, i, j, k, c0, A);
+        fetch_corners(g.psi, g.nx, g.ny, g.nz, g.px, g.py, g.pz, i, j, k, c0, A);
     }
     if (ks == CENTRE) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) B[q] = Z[q];
     } else {
-        cell_corners(g, i, j, k, cs, B);
+        fetch_corners(g.psi, g.nx, g.ny, g.nz, g.px, g.py, g.pz, i, j, k, cs, B);
     }
-    float vr, vi, gr[3], gi[3];
-    tri_corners(A, u0, vr, vi, gr, gi);
-    float t[3] = {gr[1] * gi[2] - gr[2] * gi[1], gr[2] * gi[0] - gr[0] * gi[2], gr[0] * gi[1] - gr[1] * gi[0]};
-    const float tn = sqrtf(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-    const float nr = sqrtf(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-    const float ni = sqrtf(gi[0] * gi[0] + gi[1] * gi[1] + gi[2] * gi[2]);
-    if (!(tn > 1e-6f * nr * ni) || tn == 0.f) return false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) t[a] /= tn;
-    int ax = 0;
-    if (fabsf(t[1]) < fabsf(t[ax])) ax = 1;
-    if (fabsf(t[2]) < fabsf(t[ax])) ax = 2;
-    const float uu[3] = {ax == 0 ? 1.f : 0.f, ax == 1 ? 1.f : 0.f, ax == 2 ? 1.f : 0.f};
-    float e1[3] = {t[1] * uu[2] - t[2] * uu[1], t[2] * uu[0] - t[0] * uu[2], t[0] * uu[1] - t[1] * uu[0]};
-    const float n1 = sqrtf(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) e1[a] /= n1;
-    const float e2[3] = {t[1] * e1[2] - t[2] * e1[1], t[2] * e1[0] - t[0] * e1[2], t[0] * e1[1] - t[1] * e1[0]};
-    const float d[3] = {xs[0] - x0[0], xs[1] - x0[1], xs[2] - x0[2]};
-    float y1 = d[0] * e1[0] + d[1] * e1[1] + d[2] * e1[2];
-    float y2 = d[0] * e2[0] + d[1] * e2[1] + d[2] * e2[2];
-    float xp[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xp[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
-    if (!in_patch(xp)) return false;
-    const int kp = patch_cell(xp, cp, up);
+    float vr, vi;
+    V3 gr, gi, e1, e2;
+    tri_coeffs(A, cf);
+    trilinear(cf, u0, vr, vi, gr, gi);
+    uint32_t status = 0;
+    plane_basis(gr, gi, desc, e1, e2, status);
+    if (status & VX_SAMPLE_TANGENT_FALLBACK) return false;
+    const V3 d = v3(xs.x - x0.x, xs.y - x0.y, xs.z - x0.z);
+    float y1 = dot(d, e1), y2 = dot(d, e2);
+    const V3 xp = plane_point(x0, e1, e2, y1, y2);
+    if (!in_patch(xp, box)) return false;
+    const int kp = locate(xp, box, cp, up);
     if (kp == ks || kp == k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) C[q] = kp == ks ? B[q] : A[q];
     } else {
-        cell_corners(g, i, j, k, cp, C);
+        fetch_corners(g.psi, g.nx, g.ny, g.nz, g.px, g.py, g.pz, i, j, k, cp, C);
     }
-    tri_corners(C, up, vr, vi, gr, gi);
-    const float j00 = e1[0] * gr[0] + e1[1] * gr[1] + e1[2] * gr[2], j01 = e2[0] * gr[0] + e2[1] * gr[1] + e2[2] * gr[2];
-    const float j10 = e1[0] * gi[0] + e1[1] * gi[1] + e1[2] * gi[2], j11 = e2[0] * gi[0] + e2[1] * gi[1] + e2[2] * gi[2];
-    const float det = j00 * j11 - j01 * j10;
-    if (det == 0.f) return false;
-    y1 += -(j11 * vr - j01 * vi) / det;
-    y2 += -(-j10 * vr + j00 * vi) / det;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) out[a] = x0[a] + y1 * e1[a] + y2 * e2[a];
-    if (!in_patch(out)) return false;
+    tri_coeffs(C, cf);
+    trilinear(cf, up, vr, vi, gr, gi);
+    float n1, n2, den;
+    if (!newton_dir(vr, vi, plane_jac(gr, gi, e1, e2), n1, n2, den)) return false;
+    const float p1 = n1 * den, p2 = n2 * den;
+    y1 = y1 + p1;
+    y2 = y2 + p2;
+    out = plane_point(x0, e1, e2, y1, y2);
+    if (!in_patch(out, box)) return false;
     int co[3];
     float uo[3];
-    if (patch_cell(out, co, uo) != kp) cell_corners(g, i, j, k, co, C);
-    tri_corners(C, uo, vr, vi, gr, gi);
+    if (locate(out, box, co, uo) != kp) {
+        fetch_corners(g.psi, g.nx, g.ny, g.nz, g.px, g.py, g.pz, i, j, k, co, C);
+        tri_coeffs(C, cf);
+    }
+    trilinear(cf, uo, vr, vi, gr, gi);
     rho = vr * vr + vi * vi;
+    if (max_step > 0.f && rho != 0.f) {
+        if (!newton_dir(vr, vi, plane_jac(gr, gi, e1, e2), n1, n2, den)) return false;
+        const float q1 = n1 * den, q2 = n2 * den;
+        if (!(q1 * q1 + q2 * q2 <= max_step * max_step)) return false;
+    }
     return true;
 }
 
@@ -703,7 +629,7 @@ __global__ __launch_bounds__(NT) void features_k(Geo g, const uint64_t *__restri
 __global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restrict__ cells, const uint16_t *__restrict__ desc,
                                                 const vx_sample *__restrict__ smp, const int64_t *__restrict__ count,
                                                 int64_t cap, __bf16 *feat, float *target, unsigned long long *d_n,
-                                                int64_t n_cap) {
+                                                int64_t n_cap, unsigned long long *flag) {
     const int64_t n = min(*count, cap);
     if ((int64_t)blockIdx.x * TM >= n) return;  // uniform per workgroup
     const int64_t s = (int64_t)blockIdx.x * TM + (threadIdx.x >> 2);
@@ -727,15 +653,15 @@ __global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restric
     const int lead = (int)(threadIdx.x & ~3u) & 63;
     slot = ((unsigned long long)(uint32_t)__shfl((int)(slot >> 32), lead) << 32) | (uint32_t)__shfl((int)slot, lead);
     const bool store = keep && (int64_t)slot < n_cap;
+    if (keep && c == 0 && (int64_t)slot >= n_cap) atomicOr(flag, (unsigned long long)VX_OVERFLOW_DATASET);
     gather_features(g, i, j, k, c, feat + (store ? (int64_t)slot : 0) * NIN, store);
     if (store) {
         if (c == 0) {
-            float x0, y0, z0;
-            int np;
-            first_estimate(desc[s], x0, y0, z0, np);
-            target[slot * 3 + 0] = smp[s].off[0] - x0;
-            target[slot * 3 + 1] = smp[s].off[1] - y0;
-            target[slot * 3 + 2] = smp[s].off[2] - z0;
+            uint32_t st0 = 0;
+            const vxr::V3 x0 = vxr::first_estimate(desc[s], st0);
+            target[slot * 3 + 0] = smp[s].off[0] - x0.x;
+            target[slot * 3 + 1] = smp[s].off[1] - x0.y;
+            target[slot * 3 + 2] = smp[s].off[2] - x0.z;
         }
     }
 }
@@ -761,15 +687,19 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
                                                    const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
-                                                   float4 *centre, int64_t *fb_count) {
+                                                   float4 *centre, int64_t *fb_count, unsigned long long *flag) {
     constexpr int NW = NTI / 64;
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
     __shared__ float2 sg[GT];
     __shared__ __attribute__((aligned(16))) float sB[2 * NH];          // b1 then b2
     __shared__ __attribute__((aligned(16))) float sP[NW * TM * NOUT];  // partial heads [wavefront][cell][4]
-    if (blockIdx.x == 0 && threadIdx.x == 0) *fb_count = 0;  // the fallback queue of polish_k, launched next
-    const int64_t n = min(*count, cap);
+    const int64_t cnt = *count;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *fb_count = 0;  // the fallback queue of polish_k, launched next
+        if (cnt > cap) atomicOr(flag, (unsigned long long)VX_OVERFLOW_REFINE);
+    }
+    const int64_t n = min(cnt, cap);
     const int64_t ntiles = (n + TM - 1) / TM;
     if ((int64_t)blockIdx.x >= ntiles) return;  // uniform per workgroup
     const int t = threadIdx.x, l = t & 63, w = t >> 6, n0 = 32 * w, q4 = 4 * (l >> 4);
@@ -927,8 +857,8 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict__ cells,
                                                const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
                                                int64_t cap, const float4 *__restrict__ net_out,
-                                               const float4 *__restrict__ centre, float thr, vx_sample *out,
-                                               uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
+                                               const float4 *__restrict__ centre, float thr, float max_step,
+                                               vx_sample *out, uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
                                                int64_t *fb_count) {
     const int64_t n = min(*count, cap);
     if ((int64_t)blockIdx.x * NT >= n) return;  // uniform per workgroup
@@ -939,9 +869,9 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
     if (s < n) {
         cell = cells[s];
         d = desc[s];
-        float x0, y0, z0;
-        int np;
-        first_estimate(d, x0, y0, z0, np);
+        uint32_t st0 = 0;
+        const vxr::V3 x0 = vxr::first_estimate(d, st0);
+        const int np = __popc((d | (d >> 1)) & 0x555u);  // pierced faces: nonzero 2-bit fields
         const float4 o = net_out[s];
         bool mine = np == 2 && o.w >= thr && cell < (uint64_t)g.nx * g.ny * g.nz;
         int i = 0, j = 0, k = 0;
@@ -950,16 +880,16 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
             mine = interior(g, i, j, k);
         }
         if (mine) {
-            const float x0v[3] = {x0, y0, z0};
-            const float xs[3] = {x0 + o.x, y0 + o.y, z0 + o.z};
-            float x[3], rho = 0.f;
-            mine = polish(g, i, j, k, centre + 4 * s, x0v, xs, x, rho);
+            const vxr::V3 xs = vxr::v3(x0.x + o.x, x0.y + o.y, x0.z + o.z);
+            vxr::V3 x;
+            float rho = 0.f;
+            mine = polish(g, i, j, k, d, centre + 4 * s, x0, xs, max_step, x, rho);
             if (mine) {
                 vx_sample r{};
                 r.cell = cell;
-                r.off[0] = x[0];
-                r.off[1] = x[1];
-                r.off[2] = x[2];
+                r.off[0] = x.x;
+                r.off[1] = x.y;
+                r.off[2] = x.z;
                 r.rho = rho;
                 r.iters = 1;
                 r.status = (uint16_t)VX_SAMPLE_SURROGATE;
@@ -998,7 +928,7 @@ struct vx_mlp {
     // training scratch
     __bf16 *H1 = nullptr, *G1 = nullptr, *H2 = nullptr, *G2 = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
     float *dZ3 = nullptr, *loss = nullptr;
-    // inference fallback queue (grown on demand)
+    // inference buffers, sized by vx_mlp_reserve for lists of up to fb_cap cells
     int64_t fb_cap = 0;
     float4 *net_out = nullptr;
     float4 *centre = nullptr;  // [cap][4]: the 8 corners of each listed cell, for the polish
@@ -1130,6 +1060,38 @@ extern "C" vx_status vx_mlp_destroy(vx_mlp *m) {
     return VX_OK;
 }
 
+extern "C" vx_status vx_mlp_reserve(vx_mlp *m, int64_t max_cells) {
+    if (!m) return VX_ERR_INVALID;
+    vx_handle *h = m->h;
+    h->err.clear();
+    if (max_cells < 0 || max_cells > (1LL << 36)) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_reserve: max_cells");
+    if (max_cells <= m->fb_cap) return VX_OK;
+    if (vx_status st = vx_bind(h)) return st;
+    // the old buffers may still be read by work in flight on any stream
+    if (vx_status st = vx_hip_check(h, hipDeviceSynchronize(), "vx_mlp_reserve")) return st;
+    for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index, (void *)m->net_out, (void *)m->centre}) {
+        if (!q) continue;
+        (void)hipFree(q);
+        for (auto &a : m->allocs)
+            if (a == q) a = nullptr;
+    }
+    m->fb_cell = nullptr;
+    m->fb_desc = nullptr;
+    m->fb_index = nullptr;
+    m->net_out = nullptr;
+    m->centre = nullptr;
+    m->fb_cap = 0;
+    const size_t c = (size_t)max_cells;
+    vx_status st = dalloc(m, (void **)&m->fb_cell, c * 8);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->net_out, c * sizeof(float4));
+    if (st == VX_OK) st = dalloc(m, (void **)&m->centre, c * 4 * sizeof(float4));
+    if (st == VX_OK) st = dalloc(m, (void **)&m->fb_desc, c * 2);
+    if (st == VX_OK) st = dalloc(m, (void **)&m->fb_index, c * 8);
+    if (st) return st;
+    m->fb_cap = max_cells;
+    return VX_OK;
+}
+
 extern "C" vx_status vx_mlp_get_params(vx_mlp *m, float *h_params) {
     if (!m || !h_params) return VX_ERR_INVALID;
     if (vx_status st = vx_bind(m->h)) return st;
@@ -1190,7 +1152,8 @@ extern "C" vx_status vx_mlp_dataset(vx_handle *h, vx_dims dims, const void *d_ps
     if (vx_status st = vx_bind(h)) return st;
     const unsigned blocks = (unsigned)((cap + TM - 1) / TM);
     hipLaunchKernelGGL(dataset_k, dim3(blocks), dim3(NT), 0, (hipStream_t)s, geo_of(dims, d_psi), d_cells, d_cell_desc,
-                       d_samples, d_count, cap, (__bf16 *)d_feat, d_target, (unsigned long long *)d_n, n_cap);
+                       d_samples, d_count, cap, (__bf16 *)d_feat, d_target, (unsigned long long *)d_n, n_cap,
+                       vx_overflow_flag(h));
     return vx_hip_check(h, hipGetLastError(), "dataset_k launch");
 }
 
@@ -1266,7 +1229,7 @@ extern "C" vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n
 
 extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
                                   const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
-                                  const vx_refine_params *p, vx_sample *d_out, vx_stream s) {
+                                  float max_step, const vx_refine_params *p, vx_sample *d_out, vx_stream s) {
     if (!m) return VX_ERR_INVALID;
     vx_handle *h = m->h;
     h->err.clear();
@@ -1278,40 +1241,22 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     const vx_refine_params prm = p ? *p : vx_refine_defaults();
     if (vx_status st = vx_check_refine_params(h, prm)) return st;
     if (vx_status st = vx_bind(h)) return st;
-    if (cap > m->fb_cap) {  // fallback queue sized for the whole list
-        for (void *q : {(void *)m->fb_cell, (void *)m->fb_desc, (void *)m->fb_index, (void *)m->net_out,
-                        (void *)m->centre}) {
-            if (!q) continue;
-            (void)hipFree(q);
-            for (auto &a : m->allocs)
-                if (a == q) a = nullptr;
-        }
-        m->fb_cell = nullptr;
-        m->fb_desc = nullptr;
-        m->fb_index = nullptr;
-        m->net_out = nullptr;
-        m->centre = nullptr;
-        m->fb_cap = 0;
-        vx_status st = dalloc(m, (void **)&m->fb_cell, (size_t)cap * 8);
-        if (st == VX_OK) st = dalloc(m, (void **)&m->net_out, (size_t)cap * sizeof(float4));
-        if (st == VX_OK) st = dalloc(m, (void **)&m->centre, (size_t)cap * 4 * sizeof(float4));
-        if (st == VX_OK) st = dalloc(m, (void **)&m->fb_desc, (size_t)cap * 2);
-        if (st == VX_OK) st = dalloc(m, (void **)&m->fb_index, (size_t)cap * 8);
-        if (st) return st;
-        m->fb_cap = cap;
-    }
+    if (cap > m->fb_cap)
+        return vx_fail(h, VX_ERR_INVALID, "vx_mlp_infer: capacity %lld exceeds the %lld cells reserved by vx_mlp_reserve",
+                       (long long)cap, (long long)m->fb_cap);
+    if (!(max_step >= 0.f)) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_infer: max_step must be >= 0");
     hipStream_t hs = (hipStream_t)s;
     vx_timer tm(h, hs, VX_KIND_MLP);
     const int64_t num_cu = h->num_cu > 0 ? h->num_cu : 256;
     const int64_t tiles = (cap + TM - 1) / TM;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu));
     hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
-                       d_count, cap, m->net_out, m->centre, m->fb_count);
+                       d_count, cap, m->net_out, m->centre, m->fb_count, vx_overflow_flag(h));
     tm.stop();
     vx_timer tp(h, hs, VX_KIND_POLISH);
     hipLaunchKernelGGL(polish_k, dim3((unsigned)((cap + NT - 1) / NT)), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
                        d_cell_desc, d_count, cap, (const float4 *)m->net_out, (const float4 *)m->centre, conf_threshold,
-                       d_out, m->fb_cell,
+                       max_step, d_out, m->fb_cell,
                        m->fb_desc, m->fb_index, m->fb_count);
     tp.stop();
     vx_status st = vx_hip_check(h, hipGetLastError(), "surrogate inference launch");

@@ -18,9 +18,11 @@
 // samples share nodes) when the iterate changes cell. The state machine's bookkeeping after each
 // evaluation is written as selects: loop-carried state updated under divergent branches costs
 // register copies at every merge. FP32 arithmetic throughout.
-#include "vx_internal.h"
+#include "vx_refine_math.h"
 
 namespace {
+
+using namespace vxr;
 
 constexpr int REF_THREADS = 256;  // four wavefronts per workgroup
 constexpr int REF_CHUNK = 64;     // samples a wavefront claims at a time
@@ -35,259 +37,11 @@ struct RefArgs {
     vx_sample *out;
     const int64_t *out_index;    // nullable: sample s is written to out[out_index[s]]
     unsigned long long *chunks;  // chunk counter, zero at launch
+    unsigned long long *flag;    // nullable: sticky overflow flags, VX_OVERFLOW_REFINE set if count > cap
     int nx, ny, nz;
     int px, py, pz;
     vx_refine_params p;
 };
-
-struct V3 {
-    float x, y, z;
-};
-__device__ __forceinline__ V3 v3(float a, float b, float c) { return V3{a, b, c}; }
-__device__ __forceinline__ float dot(const V3 &a, const V3 &b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ V3 crs(const V3 &a, const V3 &b) {
-    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-// hardware reciprocal square root and reciprocal (about 1 ulp): the normalisations and step
-// directions they feed are search directions, whose last-bit rounding does not move the minimum
-__device__ __forceinline__ float rsq(float a) { return __builtin_amdgcn_rsqf(a); }
-__device__ __forceinline__ float rcp(float a) { return __builtin_amdgcn_rcpf(a); }
-__device__ __forceinline__ float comp(const V3 &a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
-
-__device__ __forceinline__ int dec2(uint32_t d, int f) {
-    const uint32_t v = (d >> (2 * f)) & 3u;
-    return v == 1u ? 1 : (v == 3u ? -1 : 0);
-}
-
-// node g + c of an axis of n nodes (g in [0, n), c in [-1, 2]): wrapped if the axis is periodic,
-// else clamped. In 32-bit unsigned arithmetic, where g + c = -1 is the only value above 2^31.
-__device__ __forceinline__ uint32_t wrap(int g, int c, int n, int per) {
-    const uint32_t q = (uint32_t)g + (uint32_t)c, un = (uint32_t)n;
-    const uint32_t below = per ? un - 1u : 0u, above = per ? q - un : un - 1u;
-    return q == 0xffffffffu ? below : (q >= un ? above : q);
-}
-
-// quotient and remainder of n by d for n < 2^53 (every cell id of a grid that fits in memory):
-// an FP64 estimate off by at most one, then an integer correction
-__device__ __forceinline__ uint64_t divmod53(uint64_t n, uint64_t d, double rd, uint64_t &r) {
-    uint64_t q = (uint64_t)((double)n * rd);
-    int64_t rem = (int64_t)(n - q * d);
-    if (rem < 0) {
-        --q;
-        rem += (int64_t)d;
-    } else if (rem >= (int64_t)d) {
-        ++q;
-        rem -= (int64_t)d;
-    }
-    r = (uint64_t)rem;
-    return q;
-}
-
-// ---- arithmetic shared by the refinement kernels (each a forced-inline function, so that every
-// kernel computes the same FP32 expressions and reaches the same bits)
-
-// first estimate (Sec. 3.3.1): mean of the centres of the pierced faces (-x,+x,-y,+y,-z,+z)
-__device__ __forceinline__ V3 first_estimate(uint32_t desc, uint32_t &status) {
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    int npierced = 0;
-#pragma unroll
-    for (int fc = 0; fc < 6; ++fc) {
-        if (dec2(desc, fc) == 0) continue;
-        const int a = fc >> 1;
-        const float side = (float)(fc & 1);
-        sx += a == 0 ? side : 0.5f;
-        sy += a == 1 ? side : 0.5f;
-        sz += a == 2 ? side : 0.5f;
-        ++npierced;
-    }
-    if (npierced >= 4) status |= VX_SAMPLE_MULTI;
-    if (npierced == 0) {
-        status |= VX_SAMPLE_NO_FACES;
-        return v3(0.5f, 0.5f, 0.5f);
-    }
-    const float inv = 1.0f / (float)npierced;
-    return v3(sx * inv, sy * inv, sz * inv);
-}
-
-// The node patch of a sample, in the cell's local coordinates: [lo, hc + 1] per axis, where lo is
-// -1 if the patch reaches one node below the cell (else 0) and hc is 1 if it reaches two nodes above
-// (else 0) -- the cells of the patch are lo .. hc. Kept as floats so that the per-pass tests need no
-// decoding.
-struct Box {
-    V3 lo, hc;
-};
-
-__device__ __forceinline__ Box patch_box(int gi, int gj, int gk, int nx, int ny, int nz, int px, int py, int pz) {
-    const int g3[3] = {gi, gj, gk};
-    const int n3[3] = {nx, ny, nz};
-    const int p3[3] = {px, py, pz};
-    float lo[3], hc[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = (p3[a] || g3[a] - 1 >= 0) ? -1.f : 0.f;
-        hc[a] = (p3[a] || g3[a] + 2 < n3[a]) ? 1.f : 0.f;
-    }
-    return Box{v3(lo[0], lo[1], lo[2]), v3(hc[0], hc[1], hc[2])};
-}
-
-// the patch cell that holds point x (clamped to the patch) and the local coordinates in it;
-// returns the cell's code (cx+1) + 4 (cy+1) + 16 (cz+1)
-__device__ __forceinline__ int locate(const V3 &x, const Box &b, int c[3], float u[3]) {
-    const float xs[3] = {x.x, x.y, x.z}, lo[3] = {b.lo.x, b.lo.y, b.lo.z}, hc[3] = {b.hc.x, b.hc.y, b.hc.z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float fl = fminf(fmaxf(floorf(xs[a]), lo[a]), hc[a]);
-        c[a] = (int)fl;
-        u[a] = xs[a] - fl;
-    }
-    return (c[0] + 1) + 4 * (c[1] + 1) + 16 * (c[2] + 1);
-}
-
-// the 8 nodes of patch cell c of the sample cell at node (gi, gj, gk); corner d = dx + 2 dy + 4 dz
-__device__ __forceinline__ void fetch_corners(const float2 *psi_p, int fnx, int fny, int fnz, int fpx, int fpy,
-                                              int fpz, int gi, int gj, int gk, const int c[3], float2 v[8]) {
-    const uint64_t nx64 = (uint64_t)fnx, nxy = (uint64_t)fnx * (uint64_t)fny;
-    const uint32_t i0 = wrap(gi, c[0], fnx, fpx), i1 = wrap(gi, c[0] + 1, fnx, fpx);
-    const uint32_t j0 = wrap(gj, c[1], fny, fpy), j1 = wrap(gj, c[1] + 1, fny, fpy);
-    const uint32_t k0 = wrap(gk, c[2], fnz, fpz), k1 = wrap(gk, c[2] + 1, fnz, fpz);
-    const float2 *r00 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k0;
-    const float2 *r10 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k0;
-    const float2 *r01 = psi_p + nx64 * (uint64_t)j0 + nxy * (uint64_t)k1;
-    const float2 *r11 = psi_p + nx64 * (uint64_t)j1 + nxy * (uint64_t)k1;
-    v[0] = r00[i0];
-    v[1] = r00[i1];
-    v[2] = r10[i0];
-    v[3] = r10[i1];
-    v[4] = r01[i0];
-    v[5] = r01[i1];
-    v[6] = r11[i0];
-    v[7] = r11[i1];
-}
-
-// The trilinear interpolant of a cell as a polynomial in the local coordinates (u, v, w):
-// f = c0 + c1 u + c2 v + c3 w + c4 uv + c5 uw + c6 vw + c7 uvw, from the corners d = dx + 2 dy + 4 dz
-// (computed once per cell change, then cached)
-__device__ __forceinline__ void tri_coeffs(const float2 v[8], float2 c[8]) {
-    auto sub = [](float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); };
-    c[0] = v[0];
-    c[1] = sub(v[1], v[0]);
-    c[2] = sub(v[2], v[0]);
-    c[3] = sub(v[4], v[0]);
-    const float2 d32 = sub(v[3], v[2]), d54 = sub(v[5], v[4]), d64 = sub(v[6], v[4]), d76 = sub(v[7], v[6]);
-    c[4] = sub(d32, c[1]);
-    c[5] = sub(d54, c[1]);
-    c[6] = sub(d64, c[2]);
-    c[7] = sub(sub(d76, d54), c[4]);
-}
-
-// trilinear psi and its gradient (cell units) at local coordinates u of a cell with coefficients c
-// (nested: 11 multiply-adds per component)
-__device__ __forceinline__ void trilinear(const float2 c[8], const float u[3], float &tr, float &ti, V3 &tgr,
-                                          V3 &tgi) {
-    const float x = u[0], y = u[1], z = u[2];
-    float r[2], gx[2], gy[2], gz[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float c0 = k ? c[0].y : c[0].x, c1 = k ? c[1].y : c[1].x, c2 = k ? c[2].y : c[2].x;
-        const float c3 = k ? c[3].y : c[3].x, c4 = k ? c[4].y : c[4].x, c5 = k ? c[5].y : c[5].x;
-        const float c6 = k ? c[6].y : c[6].x, c7 = k ? c[7].y : c[7].x;
-        const float A = fmaf(c7, z, c4), B = fmaf(c5, z, c1), C = fmaf(c6, z, c2), D = fmaf(c3, z, c0);
-        const float E = fmaf(x, A, C);  // d/dy
-        r[k] = fmaf(y, E, fmaf(x, B, D));
-        gx[k] = fmaf(y, A, B);
-        gy[k] = E;
-        gz[k] = fmaf(x, fmaf(c7, y, c5), fmaf(c6, y, c3));
-    }
-    tr = r[0];
-    ti = r[1];
-    tgr = v3(gx[0], gy[0], gz[0]);
-    tgi = v3(gx[1], gy[1], gz[1]);
-}
-
-// orthonormal basis (e1, e2) of the plane normal to the pseudo-vorticity Re grad psi x Im grad psi
-// at x0; a degenerate cross product falls back to the net face flux, then to one pierced face
-__device__ __forceinline__ void plane_basis(const V3 &tgr, const V3 &tgi, uint32_t desc, V3 &e1, V3 &e2,
-                                            uint32_t &status) {
-    V3 t = crs(tgr, tgi);
-    // |t| > 1e-6 |grad Re| |grad Im|, compared squared
-    float tt = dot(t, t);
-    if (!(tt > 1e-12f * dot(tgr, tgr) * dot(tgi, tgi)) || tt == 0.f) {
-        status |= VX_SAMPLE_TANGENT_FALLBACK;
-        t = v3((float)(dec2(desc, 0) + dec2(desc, 1)), (float)(dec2(desc, 2) + dec2(desc, 3)),
-               (float)(dec2(desc, 4) + dec2(desc, 5)));
-        if (dot(t, t) == 0.f) {
-            t = v3(0.f, 0.f, 1.f);
-            for (int fc = 0; fc < 6; ++fc) {
-                const int w = dec2(desc, fc);
-                if (w != 0) {
-                    const int a = fc >> 1;
-                    t = v3(a == 0 ? (float)w : 0.f, a == 1 ? (float)w : 0.f, a == 2 ? (float)w : 0.f);
-                    break;
-                }
-            }
-        }
-        tt = dot(t, t);
-    }
-    const float itn = rsq(tt);
-    t = v3(t.x * itn, t.y * itn, t.z * itn);
-    int ax = 0;
-    if (fabsf(t.y) < fabsf(comp(t, ax))) ax = 1;
-    if (fabsf(t.z) < fabsf(comp(t, ax))) ax = 2;
-    e1 = crs(t, v3(ax == 0 ? 1.f : 0.f, ax == 1 ? 1.f : 0.f, ax == 2 ? 1.f : 0.f));
-    const float in1 = rsq(dot(e1, e1));
-    e1 = v3(e1.x * in1, e1.y * in1, e1.z * in1);
-    e2 = crs(t, e1);
-}
-
-// the point x0 + y1 e1 + y2 e2
-__device__ __forceinline__ V3 plane_point(const V3 &x0, const V3 &e1, const V3 &e2, float y1, float y2) {
-    return v3(x0.x + y1 * e1.x + y2 * e2.x, x0.y + y1 * e1.y + y2 * e2.y, x0.z + y1 * e1.z + y2 * e2.z);
-}
-
-__device__ __forceinline__ bool in_patch(const V3 &x, const Box &b) {
-    return x.x >= b.lo.x && x.x <= b.hc.x + 1.f && x.y >= b.lo.y && x.y <= b.hc.y + 1.f && x.z >= b.lo.z &&
-           x.z <= b.hc.z + 1.f;
-}
-
-// the accepted Newton step alpha (p1, p2) is shorter than tol (compared squared: no square root)
-__device__ __forceinline__ bool newton_short(float alpha, float p1, float p2, float tol) {
-    return alpha * alpha * (p1 * p1 + p2 * p2) < tol * tol;
-}
-
-// the gradients of Re psi and Im psi in the plane: J = [[e1.gr, e2.gr], [e1.gim, e2.gim]], the
-// Jacobian of (Re psi, Im psi) with respect to the in-plane coordinates (y1, y2); both step kinds
-// start from it
-struct PlaneJ {
-    float j00, j01, j10, j11;
-};
-__device__ __forceinline__ PlaneJ plane_jac(const V3 &gr, const V3 &gim, const V3 &e1, const V3 &e2) {
-    return PlaneJ{dot(e1, gr), dot(e2, gr), dot(e1, gim), dot(e2, gim)};
-}
-
-// steepest descent of |psi|^2 in the plane: gradient g = 2 J^T psi, direction (n1, n2) * den = -g / |g|,
-// gn = |g|
-__device__ __forceinline__ bool descent_dir(float vr, float vi, const PlaneJ &J, float &n1, float &n2, float &den,
-                                            float &gn) {
-    const float g1 = 2.f * (vr * J.j00 + vi * J.j10), g2 = 2.f * (vr * J.j01 + vi * J.j11);
-    const float gg = g1 * g1 + g2 * g2;
-    const float ig = rsq(gg);
-    gn = gg * ig;
-    n1 = -g1;
-    n2 = -g2;
-    den = ig;
-    return gg > 0.f && ig < INFINITY;
-}
-
-// Newton step for (Re psi, Im psi) = 0 in the plane: direction (n1, n2) * den = -J^-1 psi
-__device__ __forceinline__ bool newton_dir(float vr, float vi, const PlaneJ &J, float &n1, float &n2, float &den) {
-    const float j00 = J.j00, j01 = J.j01, j10 = J.j10, j11 = J.j11;
-    const float det = j00 * j11 - j01 * j10;
-    const float idet = rcp(det);
-    n1 = -(j11 * vr - j01 * vi);
-    n2 = -(-j10 * vr + j00 * vi);
-    den = idet;
-    return det != 0.f && fabsf(idet) < INFINITY;
-}
 
 // a wavefront-uniform 64-bit value, made visibly uniform to the compiler (so that loops and
 // branches on it stay scalar)
@@ -328,7 +82,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         if (tid < nframes) {
             const vx_ref_frame F = frames[tid];
             s_fr[tid] = F;
-            const int64_t n = min(*F.count, F.cap);
+            const int64_t cnt = *F.count;
+            const int64_t n = min(cnt, F.cap);
+            if (cnt > F.cap && blockIdx.x == 0 && A.flag) atomicOr(A.flag, (unsigned long long)VX_OVERFLOW_REFINE);
             s_items[tid] = n;
             s_cstart[tid + 1] = (n + REF_CHUNK - 1) / REF_CHUNK;
             s_rnx[tid] = 1.0 / (double)F.nx;
@@ -665,8 +421,12 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
     __shared__ float2 s_patch[REF_THREADS / SPEC_G][64];
     const int tid = threadIdx.x, lane = tid & 63, h = lane & (SPEC_G - 1), gl = lane - h;
     float2 *patch = s_patch[tid / SPEC_G];
-    if (blockIdx.x == 0 && tid == 0) *A.chunks = 0ull;  // chunk counter of the refine_k launch that follows
-    const int64_t n = min(*A.count, A.cap);
+    const int64_t cnt = *A.count;
+    if (blockIdx.x == 0 && tid == 0) {
+        *A.chunks = 0ull;  // chunk counter of the refine_k launch that follows
+        if (cnt > A.cap && A.flag) atomicOr(A.flag, (unsigned long long)VX_OVERFLOW_REFINE);
+    }
+    const int64_t n = min(cnt, A.cap);
     if (n > run_limit) return;  // a long list, refined by refine_k (uniform)
     const vx_refine_params &P = A.p;
     const int64_t ngroups = (int64_t)gridDim.x * (REF_THREADS / SPEC_G);
@@ -840,42 +600,60 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
 
 __global__ void zero_u64_k(unsigned long long *p) { *p = 0ull; }
 
+// resident workgroups per CU of a refinement kernel (at least 1); -1 on error
+template <typename K>
+int occupancy(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, REF_THREADS, 0) != hipSuccess) return -1;
+    return nb > 0 ? nb : 1;
+}
+
 // one resident round of wavefronts (they claim chunks dynamically); fewer for short lists; -1 on error
 template <typename K>
 int64_t ref_blocks(vx_handle *h, K kernel, int &per_cu, int64_t cap) {
     if (per_cu <= 0) {
-        int nb = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, REF_THREADS, 0);
-        if (e != hipSuccess) {
-            vx_hip_check(h, e, "refine_k occupancy");
+        per_cu = occupancy(kernel);
+        if (per_cu < 0) {
+            vx_fail(h, VX_ERR_DEVICE, "refinement kernel occupancy query failed");
             return -1;
         }
-        per_cu = nb > 0 ? nb : 1;
     }
     const int64_t resident = (int64_t)per_cu * (h->num_cu > 0 ? h->num_cu : 256);
     const int64_t need = (cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);  // >= one chunk per wavefront
     return std::max<int64_t>(1, std::min(need, resident));
 }
 
-// resident workgroups of refine_spec_k; -1 on error
-int64_t spec_blocks(vx_handle *h) {
-    if (h->refs_blocks_per_cu <= 0) {
-        int nb = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, refine_spec_k, REF_THREADS, 0);
-        if (e != hipSuccess) {
-            vx_hip_check(h, e, "refine_spec_k occupancy");
-            return -1;
-        }
-        h->refs_blocks_per_cu = nb > 0 ? nb : 1;
-    }
-    return (int64_t)h->refs_blocks_per_cu * (h->num_cu > 0 ? h->num_cu : 256);
+// What a launch of the two kernels of one list needs to know about the device.
+struct RefCfg {
+    int num_cu;       // compute units
+    int ref_per_cu;   // resident refine_k workgroups per CU
+    int spec_per_cu;  // resident refine_spec_k workgroups per CU
+    int refill;       // idle lanes a refine_k wavefront waits for before claiming samples
+};
+
+// The number of samples is known on the device only: refine_spec_k takes lists of at most one
+// sample per resident group and zeroes the chunk counter A.chunks, refine_k (if the capacity allows a
+// longer list) the others; each returns at once when the list is not its own.
+hipError_t refine_enqueue(const RefCfg &c, const RefArgs &A, int64_t cap, hipStream_t s) {
+    const int64_t resident = (int64_t)c.ref_per_cu * c.num_cu;
+    const int64_t need = (cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);  // >= one chunk per wavefront
+    const int64_t blocks = std::max<int64_t>(1, std::min(need, resident));
+    const int64_t sblocks = (int64_t)c.spec_per_cu * c.num_cu;
+    constexpr int64_t GPB = REF_THREADS / SPEC_G;  // groups per workgroup
+    const int64_t limit = sblocks * GPB;
+    const bool short_only = cap <= limit;
+    const int64_t sgrid = std::max<int64_t>(1, std::min(sblocks, (cap + GPB - 1) / GPB));
+    hipLaunchKernelGGL(refine_spec_k, dim3((unsigned)sgrid), dim3(REF_THREADS), 0, s, A,
+                       short_only ? INT64_MAX : limit);
+    if (!short_only)
+        hipLaunchKernelGGL(refine_k<false>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A,
+                           (const vx_ref_frame *)nullptr, 1, c.refill, limit);
+    return hipGetLastError();
 }
 
-}  // namespace
-
-vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
-                           const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
-                           const vx_refine_params &p, vx_sample *out, hipStream_t s, const int64_t *out_index) {
+RefArgs make_args(const vx_dims &d, const void *psi, const uint64_t *cells, const uint16_t *desc, const float *seed,
+                  const int64_t *count, int64_t cap, const vx_refine_params &p, vx_sample *out,
+                  const int64_t *out_index, unsigned long long *chunks, unsigned long long *flag) {
     RefArgs A;
     A.out_index = out_index;
     A.psi = (const float2 *)psi;
@@ -885,7 +663,8 @@ vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, cons
     A.count = count;
     A.cap = cap;
     A.out = out;
-    A.chunks = h->d_work;
+    A.chunks = chunks;
+    A.flag = flag;
     A.nx = d.nx;
     A.ny = d.ny;
     A.nz = d.nz;
@@ -893,24 +672,24 @@ vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, cons
     A.py = (int)((d.periodic >> 1) & 1u);
     A.pz = (int)((d.periodic >> 2) & 1u);
     A.p = p;
-    const int64_t blocks = ref_blocks(h, refine_k<false>, h->ref_blocks_per_cu, cap);
-    const int64_t sblocks = spec_blocks(h);
-    if (blocks < 0 || sblocks < 0) return VX_ERR_DEVICE;
-    // the number of samples is known on the device only: refine_spec_k takes lists of at most one
-    // sample per resident group and zeroes the chunk counter, refine_k (if the capacity allows a
-    // longer list) the others; each returns at once when the list is not its own
-    constexpr int64_t GPB = REF_THREADS / SPEC_G;  // groups per workgroup
-    const int64_t limit = sblocks * GPB;
-    const bool short_only = cap <= limit;
-    const int64_t sgrid = std::max<int64_t>(1, std::min(sblocks, (cap + GPB - 1) / GPB));
+    return A;
+}
+
+}  // namespace
+
+vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
+                           const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
+                           const vx_refine_params &p, vx_sample *out, hipStream_t s, const int64_t *out_index) {
+    if (h->ref_blocks_per_cu <= 0) h->ref_blocks_per_cu = occupancy(refine_k<false>);
+    if (h->refs_blocks_per_cu <= 0) h->refs_blocks_per_cu = occupancy(refine_spec_k);
+    if (h->ref_blocks_per_cu < 0 || h->refs_blocks_per_cu < 0)
+        return vx_fail(h, VX_ERR_DEVICE, "refinement kernel occupancy query failed");
+    const RefCfg c{h->num_cu > 0 ? h->num_cu : 256, h->ref_blocks_per_cu, h->refs_blocks_per_cu, h->ref_refill};
+    const RefArgs A = make_args(d, psi, cells, desc, seed, count, cap, p, out, out_index, h->d_work, vx_overflow_flag(h));
     vx_timer tm(h, s, VX_KIND_REFINE);
-    hipLaunchKernelGGL(refine_spec_k, dim3((unsigned)sgrid), dim3(REF_THREADS), 0, s, A,
-                       short_only ? INT64_MAX : limit);
-    if (!short_only)
-        hipLaunchKernelGGL(refine_k<false>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A,
-                           (const vx_ref_frame *)nullptr, 1, h->ref_refill, limit);
+    const hipError_t e = refine_enqueue(c, A, cap, s);
     tm.stop();
-    return vx_hip_check(h, hipGetLastError(), "refine launch");
+    return vx_hip_check(h, e, "refine launch");
 }
 
 vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
@@ -919,6 +698,7 @@ vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, in
         return vx_fail(h, VX_ERR_INVALID, "refine batch: %d frames", nframes);
     RefArgs A{};
     A.chunks = d_counter;
+    A.flag = vx_overflow_flag(h);
     A.p = p;
     const int64_t blocks = ref_blocks(h, refine_k<true>, h->refb_blocks_per_cu, total_cap);
     if (blocks < 0) return VX_ERR_DEVICE;
@@ -927,3 +707,4 @@ vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, in
                        h->ref_refill, (int64_t)-1);
     return vx_hip_check(h, hipGetLastError(), "refine_k batch launch");
 }
+

@@ -67,6 +67,11 @@ extern "C" vx_status vx_create(int device, vx_handle **out) {
         delete h;
         return VX_ERR_NOMEM;
     }
+    if (hipMemset(h->d_work, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(h->d_work);
+        delete h;
+        return VX_ERR_DEVICE;
+    }
     *out = h;
     return VX_OK;
 }
@@ -137,13 +142,34 @@ extern "C" vx_status vx_profile_read(vx_handle *h, int kind, double *total_ms, i
     return VX_OK;
 }
 
-extern "C" vx_status vx_wind_config(vx_handle *h, int rows_per_wave, int zchunk) {
+extern "C" vx_status vx_wind_config(vx_handle *h, int zchunk) {
     if (!h) return VX_ERR_INVALID;
-    if (rows_per_wave != 0) return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: rows_per_wave must be 0");
     if (zchunk < 0) return vx_fail(h, VX_ERR_INVALID, "vx_wind_config: negative zchunk");
-    h->wind_ty = rows_per_wave;
     h->wind_zc = zchunk;
     return VX_OK;
+}
+
+extern "C" vx_status vx_sync_status(vx_handle *h, vx_stream s) {
+    if (!h) return VX_ERR_INVALID;
+    h->err.clear();
+    if (vx_status st = vx_bind(h)) return st;
+    hipStream_t hs = (hipStream_t)s;
+    unsigned long long flags = 0;
+    static const unsigned long long zero = 0;
+    vx_status st = vx_hip_check(h, hipMemcpyAsync(&flags, vx_overflow_flag(h), sizeof flags, hipMemcpyDeviceToHost, hs),
+                                "vx_sync_status: read");
+    if (st == VX_OK) st = vx_hip_check(h, hipStreamSynchronize(hs), "vx_sync_status: synchronise");
+    if (st == VX_OK && flags != 0) {
+        st = vx_hip_check(h, hipMemcpyAsync(vx_overflow_flag(h), &zero, sizeof zero, hipMemcpyHostToDevice, hs),
+                          "vx_sync_status: clear");
+        if (st == VX_OK) st = vx_hip_check(h, hipStreamSynchronize(hs), "vx_sync_status: synchronise");
+        if (st == VX_OK)
+            return vx_fail(h, VX_ERR_CAPACITY, "a list was longer than its capacity:%s%s%s",
+                           (flags & VX_OVERFLOW_WIND) ? " pierced faces or cells (winding)" : "",
+                           (flags & VX_OVERFLOW_REFINE) ? " listed cells beyond the sample capacity" : "",
+                           (flags & VX_OVERFLOW_DATASET) ? " training rows beyond n_cap" : "");
+    }
+    return st;
 }
 
 // ------------------------------------------------------------------------------- validation

@@ -328,8 +328,10 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
         if (cnt == 0) return;
         wait_lds();
         unsigned long long base = 0;
-        if (lane == 0)
+        if (lane == 0) {
             base = atomicAdd(reinterpret_cast<unsigned long long *>(&A.counts[faces ? 0 : 1]), (unsigned long long)cnt);
+            if ((int64_t)base + cnt > (faces ? A.fcap : A.ccap)) atomicOr(A.flag, (unsigned long long)VX_OVERFLOW_WIND);
+        }
         base = __shfl(base, 0);
         for (int i = lane; i < cnt; i += 64) {
             const int64_t idx = (int64_t)base + i;
@@ -574,6 +576,7 @@ vx_status vx_wind_make_args(vx_handle *h, const vx_dims &d, const void *psi, con
     A.cdesc = o.d_cell_desc;
     A.ccap = o.cell_cap;
     A.counts = o.d_counts;
+    A.flag = vx_overflow_flag(h);
     A.nx = d.nx;
     A.ny = d.ny;
     A.nz = d.nz;

@@ -56,8 +56,8 @@ class Extractor:
         except Exception:
             pass
 
-    def config(self, rows_per_wave: int = 0, zchunk: int = 0):
-        vx_wind_config(self.h, rows_per_wave, zchunk)
+    def config(self, zchunk: int = 0):
+        vx_wind_config(self.h, zchunk)
 
     # ------------------------------------------------------------------ inputs
     def gen_tangle(self, tangle, stream=None):

@@ -23,9 +23,9 @@ import time
 
 import numpy as np
 
-from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, SAMPLE_SURROGATE, AdamParams, Extractor, dims, samples_to_numpy,
-               vx_mlp_create, vx_mlp_dataset, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load, vx_mlp_save,
-               vx_mlp_train_step, vx_profile_enable, vx_profile_read)
+from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_MAX_STEP, SAMPLE_SURROGATE, AdamParams, Extractor, dims,
+               samples_to_numpy, vx_mlp_create, vx_mlp_dataset, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
+               vx_mlp_reserve, vx_mlp_save, vx_mlp_train_step, vx_profile_enable, vx_profile_read)
 
 BAD = 8 | 16 | 32 | 64  # NONZERO_MIN, NOT_CONVERGED, NO_FACES, BAD_CELL
 
@@ -88,7 +88,7 @@ def train(ex: Extractor, feat, target, n: int, init_params, epochs: int = 12, ba
     return m, hist, time.perf_counter() - t0, step
 
 
-def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10):
+def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, max_step: float = MLP_MAX_STEP):
     """Plain refinement vs surrogate + fallback on every pierced cell of one field."""
     torch = ex.torch
     psi = ex.gen_tangle(tangle)
@@ -100,11 +100,13 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10):
     torch.cuda.synchronize()
     nc = int(out["counts"][1].cpu())
     cap = out["cells"].numel()
+    vx_mlp_reserve(ex.h, m, cap)
     plain = ex.alloc_samples(cap)
     sur = ex.alloc_samples(cap)
     # warm up both paths, then time each with HIP events (kernel time) and wall clock
     ex.refine(psi, out, 7, plain)
-    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur)
+    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur,
+                 max_step=max_step)
     torch.cuda.synchronize()
     vx_profile_enable(ex.h, True)
     t0 = time.perf_counter()
@@ -117,7 +119,8 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10):
     vx_profile_enable(ex.h, True)
     t0 = time.perf_counter()
     for _ in range(reps):
-        vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur)
+        vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur,
+                     max_step=max_step)
     torch.cuda.synchronize()
     sur_wall = (time.perf_counter() - t0) / reps
     net_ms, k1 = vx_profile_read(ex.h, KIND_MLP)
@@ -137,13 +140,18 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10):
         "field": f"{nx}x{ny}x{nz}",
         "cells": nc,
         "threshold": threshold,
+        "max_step": max_step,
         "surrogate_fraction": float(used.mean()),
         "fallback_fraction": float(1.0 - used.mean()),
         "median_err_surrogate_cells": float(np.median(e_sur)) if len(e_sur) else None,
         "p90_err_surrogate_cells": float(np.percentile(e_sur, 90)) if len(e_sur) else None,
         "p99_err_surrogate_cells": float(np.percentile(e_sur, 99)) if len(e_sur) else None,
+        "max_err_surrogate_cells": float(e_sur.max()) if len(e_sur) else None,
+        "surrogate_cells_above_0.02": int((e_sur > 0.02).sum()),
+        "surrogate_cells_above_1e-3": int((e_sur > 1e-3).sum()),
         "median_err_all_cells": float(np.median(e_all)),
         "p99_err_all_cells": float(np.percentile(e_all, 99)),
+        "max_err_all_cells": float(e_all.max()),
         "plain_kernel_ms": plain_ms,
         "surrogate_kernel_ms": sur_ms,
         "surrogate_net_ms": net_ms / max(k1, 1),

@@ -39,9 +39,11 @@ def upload_bf16(x):
     return torch.from_numpy(np.asarray(x, np.float32)).to(torch.bfloat16).contiguous().cuda()
 
 
-def make_mlp(ex, P, max_batch=4096):
-    from paper_1911_12070_amd import vx_mlp_create
-    return vx_mlp_create(ex.h, vxinputs.mlp_pack(P), max_batch)
+def make_mlp(ex, P, max_batch=4096, max_cells=1 << 16):
+    from paper_1911_12070_amd import vx_mlp_create, vx_mlp_reserve
+    m = vx_mlp_create(ex.h, vxinputs.mlp_pack(P), max_batch)
+    vx_mlp_reserve(ex.h, m, max_cells)
+    return m
 
 
 @pytest.mark.parametrize("n", [300, 1000])
@@ -195,6 +197,20 @@ def test_dataset_rows(ex):
         hits += 1
         assert np.allclose(Tg[r], s["off"][i] - M.first_estimate(int(cdesc[i])), atol=1e-6)
     assert hits >= 0.95 * k
+    # a row capacity below the eligible count: rows counted, the capacity flag set
+    from paper_1911_12070_amd import VX_ERR_CAPACITY, VxError, vx_sync_status
+    try:
+        vx_sync_status(ex.h)  # clears what earlier tests on this handle left
+    except VxError:
+        pass
+    n_out.zero_()
+    vx_mlp_dataset(ex.h, dims(nx, ny, nz, 7), psi, out["cells"], out["cdesc"], smp, out["counts"][1:], nc, feat,
+                   target, n_out, k // 2)
+    torch.cuda.synchronize()
+    assert int(n_out.cpu()) == k
+    with pytest.raises(VxError) as e:
+        vx_sync_status(ex.h)
+    assert e.value.status == VX_ERR_CAPACITY and "n_cap" in str(e.value)
 
 
 def test_infer_fallback_and_surrogate(ex, tmp_path):
@@ -213,7 +229,7 @@ def test_infer_fallback_and_surrogate(ex, tmp_path):
     a = samples_to_numpy(res, nc)
     assert a.tobytes() == plain.tobytes(), "threshold above 1 must reproduce the plain refinement"
     res.fill_(0)
-    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], nc, 0.0, res)
+    vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], nc, 0.0, res, max_step=0.0)
     feat = torch.zeros((nc, 128), dtype=torch.bfloat16, device="cuda")
     vx_mlp_features(ex.h, d, psi, out["cells"], out["counts"][1:], nc, feat)
     fo = torch.zeros((nc, 4), dtype=torch.float32, device="cuda")
@@ -241,6 +257,29 @@ def test_infer_fallback_and_surrogate(ex, tmp_path):
     log(f"polish: worst difference from the oracle {worst:.2e}")
     assert worst < 1e-4
     assert b[~sur].tobytes() == plain[~sur].tobytes()
+    # the acceptance bound: a polished point is kept only if the Newton step that would follow it is
+    # at most max_step cells; the rest go to the plain refinement, bit for bit
+    for max_step in (0.05, 0.005):
+        res.fill_(0)
+        vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], nc, 0.0, res, max_step=max_step)
+        torch.cuda.synchronize()
+        c = samples_to_numpy(res, nc)
+        kept = (c["status"] & SAMPLE_SURROGATE) != 0
+        assert not (kept & ~sur).any()
+        assert np.array_equal(c["off"][kept], b["off"][kept])
+        assert c[~kept].tobytes() == plain[~kept].tobytes()
+        checked = 0
+        for i in np.nonzero(sur)[0][:600]:
+            x0 = M.first_estimate(int(cdesc[i]))
+            re, im = oracle.gather_patch(psi_np, int(cells[i]))
+            start = (x0.astype(np.float32) + fo[i, :3]).astype(np.float64)
+            _, _, nxt = M.polish(re, im, int(cdesc[i]), start, with_step=True)
+            if abs(nxt - max_step) < 1e-3 * max_step:
+                continue  # too close to the bound for FP32 against FP64
+            assert kept[i] == (nxt <= max_step), (i, nxt, max_step)
+            checked += 1
+        log(f"max_step {max_step}: {kept.sum()} of {sur.sum()} polished points kept, {checked} checked")
+        assert checked > 100 and 0 < kept.sum() < sur.sum()
     path = str(tmp_path / "w.bin")
     vx_mlp_save(ex.h, m, path)
     m2 = make_mlp(ex, vxinputs.mlp_init(99))
@@ -273,7 +312,7 @@ def test_infer_edge_cases(ex):
 
     def infer(cnt, cap):
         res = torch.full((nc, 8), -7, dtype=torch.int32, device="cuda")
-        vx_mlp_infer(ex.h, m, d, psi, cells, out["cdesc"], cnt, cap, 0.0, res)
+        vx_mlp_infer(ex.h, m, d, psi, cells, out["cdesc"], cnt, cap, 0.0, res, max_step=0.0)
         torch.cuda.synchronize()
         return res
 

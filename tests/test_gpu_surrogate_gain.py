@@ -30,6 +30,7 @@ def test_trained_surrogate_gain():
     import torch
     from paper_1911_12070_amd import (KIND_MLP, KIND_POLISH, KIND_REFINE, SAMPLE_SURROGATE, Extractor, dims,
                                       samples_to_numpy, vx_mlp_create, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
+                                      vx_mlp_reserve,
                                       vx_profile_enable, vx_profile_read)
     ex = Extractor(0)
     psi = ex.gen_tangle(vxinputs.tangle_512())
@@ -61,12 +62,14 @@ def test_trained_surrogate_gain():
     good = (P["status"] & (8 | 16 | 32 | 64)) == 0
 
     zero = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    vx_mlp_reserve(ex.h, zero, cap)
     z = ex.alloc_samples(cap)
-    vx_mlp_infer(ex.h, zero, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, z)
+    vx_mlp_infer(ex.h, zero, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, z, max_step=0.0)
     trained = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    vx_mlp_reserve(ex.h, trained, cap)
     vx_mlp_load(ex.h, trained, WEIGHTS)
     a = ex.alloc_samples(cap)
-    vx_mlp_infer(ex.h, trained, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, a)
+    vx_mlp_infer(ex.h, trained, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, a, max_step=0.0)
     b = ex.alloc_samples(cap)
     t_sur = run(lambda: vx_mlp_infer(ex.h, trained, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.9, b),
                 [KIND_MLP, KIND_POLISH, KIND_REFINE])

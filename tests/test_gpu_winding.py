@@ -91,16 +91,16 @@ def _field(dims, kind, seed):
 
 
 @pytest.mark.parametrize("dims,periodic,kind,seed", CASES)
-@pytest.mark.parametrize("ty,zc", [(0, 0), (0, 3), (0, 1)])
-def test_winding_parity(ex, dims, periodic, kind, seed, ty, zc):
-    log(f"winding {dims} periodic={periodic} {kind} ty={ty} zc={zc}")
+@pytest.mark.parametrize("zc", [0, 3, 1])
+def test_winding_parity(ex, dims, periodic, kind, seed, zc):
+    log(f"winding {dims} periodic={periodic} {kind} zc={zc}")
     psi = _field(dims, kind, seed)
     W = oracle.winding(psi, periodic)
-    ex.config(ty, zc)
+    ex.config(zc)
     try:
         out = run_winding(ex, to_dev(psi), periodic)
     finally:
-        ex.config(0, 0)
+        ex.config(0)
     assert_winding_equal(out, W)
 
 
@@ -133,6 +133,47 @@ def test_capacity_overflow_keeps_true_counts(ex):
     c = out["cells"].cpu().numpy().astype(np.uint64)
     assert np.isin(f, W.faces).all() and len(np.unique(f)) == 7
     assert np.isin(c, W.cells).all() and len(np.unique(c)) == 5
+
+
+def test_capacity_status_is_sticky_until_read(ex):
+    """A list longer than its capacity sets the handle's capacity flag on the device; vx_sync_status
+    reports it once (VX_ERR_CAPACITY) and clears it. Zero capacities, the refinement's sample
+    capacity below the listed count, and the surrogate dataset's row capacity all count."""
+    import torch
+    from paper_1911_12070_amd import VX_ERR_CAPACITY, VxError, dims, vx_refine, vx_sync_status, vx_winding
+    t = vxinputs.make_tangle((64, 64, 64), 256, (3, 8), 33)
+    psi = to_dev(vxinputs.eval_tangle(t))
+    try:
+        vx_sync_status(ex.h)  # clears what earlier tests on this handle left (their overflow tests)
+    except VxError:
+        pass
+    full = run_winding(ex, psi)
+    vx_sync_status(ex.h)  # room for every face and cell: no overflow
+    nf, nc = (int(v) for v in full["counts"].cpu())
+    assert nf > 0 and nc > 0
+    # capacity 0 on both lists (no list buffers at all)
+    counts = torch.zeros(2, dtype=torch.int64, device="cuda:0")
+    vx_winding(ex.h, dims(64, 64, 64), psi, counts)
+    torch.cuda.synchronize()
+    assert tuple(int(v) for v in counts.cpu()) == (nf, nc)  # true counts still written
+    with pytest.raises(VxError) as e:
+        vx_sync_status(ex.h)
+    assert e.value.status == VX_ERR_CAPACITY and "winding" in str(e.value)
+    vx_sync_status(ex.h)  # read once, then cleared
+    # the cell list fits, the face list does not
+    run_winding(ex, psi, face_cap=nf - 1, cell_cap=nc)
+    with pytest.raises(VxError):
+        vx_sync_status(ex.h)
+    run_winding(ex, psi, face_cap=nf, cell_cap=nc)
+    vx_sync_status(ex.h)
+    # refinement: sample capacity below the listed count
+    smp = ex.alloc_samples(nc)
+    vx_refine(ex.h, dims(64, 64, 64), psi, full["cells"], full["cdesc"], full["counts"][1:], smp, cap=nc - 1)
+    with pytest.raises(VxError) as e:
+        vx_sync_status(ex.h)
+    assert e.value.status == VX_ERR_CAPACITY and "sample capacity" in str(e.value)
+    vx_refine(ex.h, dims(64, 64, 64), psi, full["cells"], full["cdesc"], full["counts"][1:], smp, cap=nc)
+    vx_sync_status(ex.h)
 
 
 def test_invalid_arguments_are_rejected(ex):

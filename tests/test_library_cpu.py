@@ -42,7 +42,7 @@ def test_status_strings_and_defaults():
 def test_null_handle_is_rejected():
     import paper_1911_12070_amd as vx
     lib = vx.lib()
-    assert lib.vx_wind_config(None, 1, 0) == vx.VX_ERR_INVALID
+    assert lib.vx_wind_config(None, 0) == vx.VX_ERR_INVALID
     assert lib.vx_profile_enable(None, 1) == vx.VX_ERR_INVALID
     assert lib.vx_destroy(None) == vx.VX_OK
     d = vx.dims(8, 8, 8)

@@ -138,3 +138,42 @@ def test_polish_degenerate_cases():
     re = np.zeros((4, 4, 4))
     im = np.zeros((4, 4, 4))
     assert M.polish(re, im, 0b01 | 0b11 << 2, [0.5, 0.5, 0.5]) is None  # no pseudo-vorticity
+
+
+def test_newton_step_estimates_the_distance_to_the_core():
+    """For linear psi the Newton step from any point of the plane is exact, so its length is the
+    distance to the core's point in the plane; the acceptance bound of the polish then rejects
+    exactly the starts whose step is longer than max_step (here on a field with a bilinear term,
+    where one Newton step does not land exactly and the following step is the remaining error)."""
+    rng = np.random.default_rng(22)
+    idx = np.arange(4) - 1.0
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    for trial in range(20):
+        a, b = rng.normal(size=3), rng.normal(size=3)
+        p = rng.uniform(0.3, 0.7, 3)
+        X = np.stack([xx, yy, zz], -1) - p
+        re, im = X @ a, X @ b
+        x0 = np.array([0.5, 0.5, 0.5])
+        t = np.cross(a, b)
+        t /= np.linalg.norm(t)
+        u = np.zeros(3)
+        u[int(np.argmin(np.abs(t)))] = 1
+        e1 = np.cross(t, u)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(t, e1)
+        core = p + ((x0 - p) @ t) * t  # the nodal line's point in the plane through x0
+        y = rng.normal(0, 0.3, 2)
+        x = x0 + y[0] * e1 + y[1] * e2
+        assert abs(M.newton_step(re, im, e1, e2, x) - np.linalg.norm(x - core)) < 1e-12
+    # bilinear term: psi = (x - 1/2) + i (y - 1/2) + 0.4 (x - 1/2)(y - 1/2); z-line through the centre
+    re = (xx - 0.5) + 0.4 * (xx - 0.5) * (yy - 0.5)
+    im = (yy - 0.5) + 0 * zz
+    desc = 0b01 << 8 | 0b01 << 10  # -z and +z faces pierced (winding +1): x0 = centre, plane z = 1/2
+    start = np.array([0.8, 0.25, 0.5])
+    x, rho, nxt = M.polish(re, im, desc, start, with_step=True)
+    assert abs(x[2] - 0.5) < 1e-15 and nxt > 1e-4 and rho > 0
+    assert M.polish(re, im, desc, start, max_step=0.5 * nxt) is None
+    x2, rho2 = M.polish(re, im, desc, start, max_step=2 * nxt)
+    assert np.array_equal(x2, x)
+    # the step after the polish estimates the remaining distance to the core at (1/2, 1/2, 1/2)
+    assert 0.5 < nxt / np.linalg.norm(x - 0.5) < 2.0
