@@ -199,6 +199,22 @@ vx_status vx_refine(vx_handle *h, vx_dims dims, const void *d_psi, const uint64_
                     const uint16_t *d_cell_desc, const float *d_seed_off, const int64_t *d_count,
                     int64_t cap, const vx_refine_params *p, vx_sample *d_out, vx_stream s);
 
+/* The refinement of vx_refine for callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): no handle, and no allocation at any
+ * point -- not even at its first call. Same kernels, same results bit for bit as vx_refine with the
+ * same arguments, on the current HIP device and stream s. The scratch that vx_refine keeps in its
+ * handle (the work counter of the refinement kernels) is a fixed 256-byte device array of the
+ * library, one copy per device, held until the process ends; it does not grow with the list, so
+ * any cap is accepted. The first call on a device looks up that array's address and the launch
+ * figures (host-side queries only) and keeps them. Every call on one device shares the array: calls
+ * that overlap in time on one device (two streams, two threads) race and give wrong samples.
+ * Overflow (*d_count > cap) refines the first cap cells and sets no flag (there is no handle).
+ * Errors: VX_ERR_INVALID (arguments, checked on the host), VX_ERR_DEVICE (a HIP call failed),
+ * VX_ERR_UNSUPPORTED (device index >= 64); no error detail is kept. */
+vx_status vx_refine_noalloc(vx_dims dims, const void *d_psi, const uint64_t *d_cells, const uint16_t *d_cell_desc,
+                            const float *d_seed_off, const int64_t *d_count, int64_t cap,
+                            const vx_refine_params *p, vx_sample *d_out, vx_stream s);
+
 /* ------------------------------------------------------------------------------------------
  * Learned surrogate of the refinement (an extension of the method; the plain refinement above
  * labels its training data, is the reference for its error and takes over below a confidence

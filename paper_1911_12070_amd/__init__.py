@@ -30,6 +30,7 @@ KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH = 0, 1, 2, 3, 4
 # every symbol include/vx.h declares
 EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
+           "vx_refine_noalloc",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
@@ -129,6 +130,8 @@ def lib() -> ctypes.CDLL:
         L.vx_refine_defaults.restype = RefineParams
         L.vx_refine.argtypes = [P, Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
         L.vx_refine.restype = st
+        L.vx_refine_noalloc.argtypes = [Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
+        L.vx_refine_noalloc.restype = st
         L.vx_batch_create.argtypes = [P, ctypes.POINTER(Frame), i, ctypes.POINTER(RefineParams), ctypes.POINTER(P)]
         L.vx_batch_create.restype = st
         L.vx_batch_launch.argtypes = [P, P]
@@ -254,6 +257,17 @@ def vx_refine(h, d: Dims, psi, cells, cdesc, count, out, params: RefineParams | 
     prm = params if params is not None else vx_refine_defaults()
     _check(h, lib().vx_refine(h, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(seed), _ptr(count), cap,
                               ctypes.byref(prm), _ptr(out), _stream(stream)), "vx_refine")
+
+
+def vx_refine_noalloc(d: Dims, psi, cells, cdesc, count, out, params: RefineParams | None = None, seed=None,
+                      stream=None, cap: int | None = None):
+    """vx_refine without a handle or any allocation (on the current device; see include/vx.h)."""
+    cap = int(out.numel() * out.element_size() // 32) if cap is None else int(cap)
+    prm = params if params is not None else vx_refine_defaults()
+    st = lib().vx_refine_noalloc(d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(seed), _ptr(count), cap,
+                                 ctypes.byref(prm), _ptr(out), _stream(stream))
+    if st != VX_OK:
+        raise VxError(st, f"vx_refine_noalloc: {lib().vx_status_str(st).decode()}")
 
 
 def winding_out(counts, wind=None, faces=None, fsign=None, cells=None, cdesc=None) -> WindingOut:

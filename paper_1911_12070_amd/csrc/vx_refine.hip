@@ -18,6 +18,8 @@
 // samples share nodes) when the iterate changes cell. The state machine's bookkeeping after each
 // evaluation is written as selects: loop-carried state updated under divergent branches costs
 // register copies at every merge. FP32 arithmetic throughout.
+#include <mutex>
+
 #include "vx_refine_math.h"
 
 namespace {
@@ -708,3 +710,68 @@ vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, in
     return vx_hip_check(h, hipGetLastError(), "refine_k batch launch");
 }
 
+// ---------------------------------------------------------------------------------------------
+// Refinement without any allocation (vx_refine_noalloc): the scratch that vx_refine keeps in the
+// handle's workspace -- the chunk counter that refine_spec_k zeroes and refine_k's wavefronts claim
+// work from -- lives here in a fixed device array instead, one copy per device. Its device address
+// is looked up once per device (the array's name is a host-side stand-in in host code and must never
+// be passed to a kernel), together with the occupancy figures the launch needs, so that a call
+// makes no allocation and no handle is needed.
+namespace {
+
+constexpr int NOALLOC_SCRATCH_WORDS = 32;  // 256 bytes; word 0 = chunk counter
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_SCRATCH_WORDS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoallocDev {
+    bool ready = false;
+    unsigned long long *scratch = nullptr;  // device address of this device's copy of `scratch`
+    RefCfg cfg{};
+};
+std::mutex g_noalloc_mu;
+NoallocDev g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Set-up of the current device (its first call): the scratch array's device address and the launch
+// figures. Returns VX_OK or an error status.
+vx_status noalloc_setup(int dev, NoallocDev &nd) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return VX_ERR_DEVICE;
+    int num_cu = 0;
+    if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || num_cu <= 0)
+        return VX_ERR_DEVICE;
+    const int r = occupancy(refine_k<false>), sp = occupancy(refine_spec_k);
+    if (r < 0 || sp < 0) return VX_ERR_DEVICE;
+    nd.scratch = (unsigned long long *)ptr;
+    nd.cfg = RefCfg{num_cu, r, sp, 8};
+    nd.ready = true;
+    return VX_OK;
+}
+
+}  // namespace
+
+extern "C" vx_status vx_refine_noalloc(vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                                       const uint16_t *d_cell_desc, const float *d_seed_off, const int64_t *d_count,
+                                       int64_t cap, const vx_refine_params *p, vx_sample *d_out, vx_stream s) {
+    if (vx_check_dims(nullptr, dims) != VX_OK) return VX_ERR_INVALID;
+    if (cap < 0) return VX_ERR_INVALID;
+    if (cap == 0) return VX_OK;
+    if (!d_psi || !d_cells || !d_cell_desc || !d_count || !d_out) return VX_ERR_INVALID;
+    const vx_refine_params prm = p ? *p : vx_refine_defaults();
+    if (vx_check_refine_params(nullptr, prm) != VX_OK) return VX_ERR_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return VX_ERR_DEVICE;
+    if (dev >= NOALLOC_MAX_DEVICES) return VX_ERR_UNSUPPORTED;
+    RefCfg cfg;
+    unsigned long long *scr;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        NoallocDev &nd = g_noalloc[dev];
+        if (!nd.ready)
+            if (vx_status st = noalloc_setup(dev, nd)) return st;
+        cfg = nd.cfg;
+        scr = nd.scratch;
+    }
+    const RefArgs A = make_args(dims, d_psi, d_cells, d_cell_desc, d_seed_off, d_count, cap, prm, d_out, nullptr, scr,
+                                nullptr);
+    return refine_enqueue(cfg, A, cap, (hipStream_t)s) == hipSuccess ? VX_OK : VX_ERR_DEVICE;
+}
