@@ -8,7 +8,8 @@ refinement of every pierced cell, all in the library's HIP kernels, inputs resid
 Prints one JSON line. `roofline` describes the dominant kernel (winding + compaction): algorithmic
 bytes per launch (8 B psi read + 1 B packed write per node, plus the list entries) over its average
 duration measured with HIP events on the launch stream inside the timed region. `cpu_baseline` is
-the CPU oracle (single-threaded C) timed on a sub-block of the same field.
+the CPU oracle (plain C) timed on a 256^3 block of the same field's bytes, on one host thread and on
+all of them (median of 5 runs each), with the host's CPU model and thread count.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 
@@ -58,43 +59,72 @@ def traffic_record(grid: int):
         return None
 
 
-def cpu_baseline(tangle, block: int = 128, budget_s: float = 12.0, label: str | None = None):
-    """Oracle (plain C, one thread) on a block^3 sub-block of the benchmark field: winding + pierced
-    lists of the block (taken as a periodic grid: the per-node work is the same) and refinement of
-    every pierced cell. Repeated until `budget_s` of CPU time is spent."""
+def host_info():
+    """CPU model and the number of host threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def cpu_baseline(block, label: str, runs: int = 5):
+    """The CPU oracle (plain C, FP64 refinement) on `block`, a cube of psi bytes copied back from the
+    GPU, taken as a periodic grid (the per-node work is the same as inside the big grid): winding +
+    pierced lists (z-slabs of 16 planes) and the refinement of every pierced cell (contiguous chunks of
+    the list), once on one thread and once on every host thread, median of `runs` runs each."""
     import numpy as np
 
     import oracle
-    import vxinputs
-    sub = vxinputs.eval_tangle(tangle, (0, 0, 0, block, block, block))
-    t_w = t_r = 0.0
-    reps = 0
-    ncell = 0
-    t0 = time.perf_counter()
-    while True:
+
+    model, nthreads = host_info()
+    nodes = int(block.size)
+
+    def once(threads):
         a = time.perf_counter()
-        W = oracle.winding(sub)
+        C, D = [], []
+        for k0, k1, pk, cd in oracle.winding_slabs(block, 7, threads=threads, slab=16):
+            _, _, c, d = oracle.lists_from_packed(pk, cd, k0 * block.shape[1] * block.shape[2])
+            C.append(c)
+            D.append(d)
+        cells, cdesc = np.concatenate(C), np.concatenate(D)
         b = time.perf_counter()
-        oracle.refine(sub, W.cells, W.cdesc)
+        oracle.refine(block, cells, cdesc, threads=threads)
         c = time.perf_counter()
-        t_w += b - a
-        t_r += c - b
-        ncell = len(W.cells)
-        reps += 1
-        if c - t0 > budget_s or reps >= 200:
-            break
-    nodes = block ** 3
-    step_s = (t_w + t_r) / reps
+        return b - a, c - b, len(cells)
+
+    res = {}
+    for key, th in (("one_thread", 1), ("all_threads", nthreads)):
+        runs_ = [once(th) for _ in range(runs)]
+        tw = float(np.median([r[0] for r in runs_]))
+        tr = float(np.median([r[1] for r in runs_]))
+        tt = float(np.median([r[0] + r[1] for r in runs_]))
+        ncell = runs_[0][2]
+        res[key] = {"threads": th, "cells_per_s": nodes / tt, "winding_cells_per_s": nodes / tw,
+                    "refine_samples_per_s": ncell / tr if tr > 0 else None, "median_step_s": tt}
+    allc = res["all_threads"]
     return {
-        "value": nodes / step_s,
+        "value": allc["cells_per_s"],
         "unit": "cells/s",
-        "cores": 1,
+        "cores": nthreads,
         "kind": "oracle",
-        "sample": f"{label or f'{block}^3 sub-block of the benchmark field'} ({nodes} cells, {ncell} pierced); winding + "
-                  f"pierced lists + FP64 refinement of every pierced cell; {reps} repetitions, "
-                  f"{t_w + t_r:.1f} s total",
-        "winding_cells_per_s": nodes * reps / t_w,
-        "refine_samples_per_s": ncell * reps / t_r if t_r > 0 else None,
+        "sample": f"{label} ({nodes} cells, {ncell} pierced) taken as a periodic grid; winding + pierced lists + "
+                  f"FP64 refinement of every pierced cell; median of {runs} runs on {nthreads} threads "
+                  f"(and on one thread: one_thread)",
+        "cpu_model": model,
+        "nproc": nthreads,
+        "winding_cells_per_s": allc["winding_cells_per_s"],
+        "refine_samples_per_s": allc["refine_samples_per_s"],
+        "one_thread": res["one_thread"],
     }
 
 
@@ -255,8 +285,8 @@ def bench_series(args):
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        f128 = next(t for t in tangles if t.dims[0] == 128)
-        res["cpu_baseline"] = cpu_baseline(f128, block=128, label="one whole 128^3 frame of the series")
+        f256 = next(f for f, t in enumerate(tangles) if t.dims[0] == 256)
+        res["cpu_baseline"] = cpu_baseline(psis[f256].cpu().numpy(), "one whole 256^3 frame of the series")
     batch.close()
     ex.close()
     print(json.dumps(res))
@@ -388,12 +418,14 @@ def main():
     del out, samples
     torch.cuda.empty_cache()
     res["pipelined"] = bench_pipeline(ex, psi, args.steps, args.warmup, cap, wl, N)
+    B = min(256, N)
+    block = psi[:B, :B, :B].cpu().numpy() if not args.no_cpu_baseline else None
     del psi
     torch.cuda.empty_cache()
     res["surrogate"] = bench_surrogate(ex)
-    if not args.no_cpu_baseline:
+    if block is not None:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(tangle)
+        res["cpu_baseline"] = cpu_baseline(block, f"the {B}^3 corner block of the benchmark field")
     ex.close()
     print(json.dumps(res))
 

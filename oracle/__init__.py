@@ -88,7 +88,7 @@ def _load():
         lib.vxo_winding_box.argtypes = [i, i, i, ctypes.c_uint, i, i, i, i, i, i, P, P, P, P]
         lib.vxo_winding_box.restype = None
         lib.vxo_refine.argtypes = [i, i, i, ctypes.c_uint, P, ctypes.c_int64, P, P,
-                                   ctypes.POINTER(_RefineParams), P, P, P, P]
+                                   ctypes.POINTER(_RefineParams), P, P, P, P, P]
         lib.vxo_refine.restype = None
         lib.vxo_refine_one.argtypes = [P, P, P, P, ctypes.c_uint, ctypes.POINTER(_RefineParams),
                                        P, P, P, P]
@@ -155,19 +155,82 @@ def winding(psi: np.ndarray, periodic: int = 7) -> Winding:
     return Winding(w, packed, faces[:nf], fsign[:nf], cells[:nc], cdesc[:nc])
 
 
-def winding_box(sub: np.ndarray, dims, origin, periodic: int = 7):
+def winding_box(sub: np.ndarray, dims, origin, periodic: int = 7, want_w: bool = True):
     """Windings of the nodes of a box from the box values plus one node in each positive
-    direction. sub: complex64 (bz+1, by+1, bx+1), already wrapped. Returns (w, packed, cdesc)."""
+    direction. sub: complex64 (bz+1, by+1, bx+1), already wrapped. Returns (w, packed, cdesc)
+    (w is None unless want_w)."""
     nx, ny, nz = dims
     bz, by, bx = (s - 1 for s in sub.shape)
     f = _f32pairs(sub)
-    w = np.zeros((bz, by, bx, 3), np.int8)
+    w = np.zeros((bz, by, bx, 3), np.int8) if want_w else None
     packed = np.zeros((bz, by, bx), np.uint8)
     cdesc = np.zeros((bz, by, bx), np.uint16)
     x0, y0, z0 = origin
-    _load().vxo_winding_box(nx, ny, nz, periodic, x0, y0, z0, bx, by, bz, _p(f), _p(w), _p(packed),
-                            _p(cdesc))
+    _load().vxo_winding_box(nx, ny, nz, periodic, x0, y0, z0, bx, by, bz, _p(f),
+                            _p(w) if w is not None else None, _p(packed), _p(cdesc))
     return w, packed, cdesc
+
+
+def _slab_sub(psi: np.ndarray, k0: int, k1: int, periodic: int) -> np.ndarray:
+    """Planes k0 .. k1 of a grid plus one node in each positive direction, wrapped where the axis is
+    periodic (an open axis repeats its last node: those values are never read)."""
+    nz, ny, nx = psi.shape
+    kk = np.arange(k0, k1 + 1)
+    kk = kk % nz if periodic & 4 else np.minimum(kk, nz - 1)
+    jj = np.arange(ny + 1) % ny if periodic & 2 else np.minimum(np.arange(ny + 1), ny - 1)
+    ii = np.arange(nx + 1) % nx if periodic & 1 else np.minimum(np.arange(nx + 1), nx - 1)
+    return psi[kk][:, jj][:, :, ii]
+
+
+def lists_from_packed(packed: np.ndarray, cdesc: np.ndarray, base: int = 0):
+    """Pierced faces (ids 3n+a ascending, signs) and pierced cells (ids ascending, descriptors) of a
+    run of nodes starting at node id `base`, from its packed bytes and cell descriptors."""
+    pk = packed.reshape(-1)
+    cd = cdesc.reshape(-1)
+    ids, signs = [], []
+    for a in range(3):
+        v = (pk >> (2 * a)) & 3
+        n = np.flatnonzero(v)
+        ids.append(3 * (n.astype(np.uint64) + np.uint64(base)) + np.uint64(a))
+        signs.append(np.where(v[n] == 1, 1, -1).astype(np.int8))
+    fid = np.concatenate(ids)
+    fs = np.concatenate(signs)
+    o = np.argsort(fid, kind="stable")
+    cn = np.flatnonzero(pk & 0x40)
+    return fid[o], fs[o], cn.astype(np.uint64) + np.uint64(base), cd[cn]
+
+
+def winding_slabs(psi: np.ndarray, periodic: int = 7, threads: int = 1, slab: int = 16):
+    """The whole-grid winding pass computed slab by slab (z-slabs of `slab` planes, in `threads`
+    host threads) with the box evaluation, which gives node for node what vxo_winding gives.
+    Yields (k0, k1, packed, cdesc) per slab in plane order."""
+    from concurrent.futures import ThreadPoolExecutor
+    nz, ny, nx = psi.shape
+
+    def one(k0):
+        k1 = min(nz, k0 + slab)
+        sub = _slab_sub(psi, k0, k1, periodic)
+        _, packed, cdesc = winding_box(sub, (nx, ny, nz), (0, 0, k0), periodic, want_w=False)
+        return k0, k1, packed, cdesc
+
+    starts = list(range(0, nz, slab))
+    if threads <= 1:
+        for k0 in starts:
+            yield one(k0)
+        return
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        # bounded look-ahead: at most 2 * threads slabs in flight
+        pending = []
+        it = iter(starts)
+        for k0 in it:
+            pending.append(ex.submit(one, k0))
+            if len(pending) >= 2 * threads:
+                break
+        for k0 in it:
+            yield pending.pop(0).result()
+            pending.append(ex.submit(one, k0))
+        for f in pending:
+            yield f.result()
 
 
 # ----------------------------------------------------------------------------------------------
@@ -180,10 +243,13 @@ class Samples:
     rho: np.ndarray     # float64 |psi|^2 at x
     iters: np.ndarray   # int32
     status: np.ndarray  # int32 status bits
+    cond: np.ndarray    # float64 condition number of the in-plane Jacobian at x (diagnostic)
 
 
 def refine(psi: np.ndarray, cells: np.ndarray, cdesc: np.ndarray, params: RefineParams | None = None,
-           periodic: int = 7) -> Samples:
+           periodic: int = 7, threads: int = 1) -> Samples:
+    """Refine the listed cells; with threads > 1 the list is cut into contiguous chunks refined in
+    host threads (each sample is independent, so the results are the same)."""
     params = params or RefineParams()
     nz, ny, nx = psi.shape
     f = _f32pairs(psi)
@@ -194,10 +260,23 @@ def refine(psi: np.ndarray, cells: np.ndarray, cdesc: np.ndarray, params: Refine
     rho = np.zeros(n, np.float64)
     iters = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
+    cond = np.zeros(n, np.float64)
     pr = params.c()
-    _load().vxo_refine(nx, ny, nz, periodic, _p(f), n, _p(cells), _p(cdesc), ctypes.byref(pr),
-                       _p(x), _p(rho), _p(iters), _p(status))
-    return Samples(x, rho, iters, status)
+    lib = _load()
+
+    def run(a, b):
+        if b > a:
+            lib.vxo_refine(nx, ny, nz, periodic, _p(f), b - a, _p(cells[a:]), _p(cdesc[a:]), ctypes.byref(pr),
+                           _p(x[a:]), _p(rho[a:]), _p(iters[a:]), _p(status[a:]), _p(cond[a:]))
+
+    if threads <= 1 or n < 2 * threads:
+        run(0, n)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        step = (n + 4 * threads - 1) // (4 * threads)
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda a: run(a, min(n, a + step)), range(0, n, step)))
+    return Samples(x, rho, iters, status, cond)
 
 
 def refine_patch(re: np.ndarray, im: np.ndarray, desc: int, params: RefineParams | None = None,

@@ -319,7 +319,7 @@ static int dec2(unsigned desc, int f) {
  *  Trial points outside the patch count as rejected trials (status BOUNDARY).
  */
 void vxo_refine_patch(const patch_t *p, unsigned desc, const vxo_refine_params *prm, double xout[3],
-                      double *rho_out, int *iters_out, int *status_out) {
+                      double *rho_out, int *iters_out, int *status_out, double *cond_out) {
     static const double ctr[6][3] = {{0, .5, .5}, {1, .5, .5}, {.5, 0, .5},
                                      {.5, 1, .5}, {.5, .5, 0}, {.5, .5, 1}};
     int status = 0, npierced = 0;
@@ -475,6 +475,16 @@ void vxo_refine_patch(const patch_t *p, unsigned desc, const vxo_refine_params *
     }
     if (f > prm->rho_tol) status |= ST_NONZERO_MIN;
     if (!converged && f > prm->rho_tol) status |= ST_NOT_CONVERGED;
+    if (cond_out) {
+        /* diagnostic only: 2-norm condition number of the in-plane Jacobian of (Re psi, Im psi) at the
+         * result, sigma_max / sigma_min from the 2x2 singular values (inf when singular) */
+        double j00 = dot3(e1, gr), j01 = dot3(e2, gr), j10 = dot3(e1, gi), j11 = dot3(e2, gi);
+        double fro2 = j00 * j00 + j01 * j01 + j10 * j10 + j11 * j11;
+        double det = fabs(j00 * j11 - j01 * j10);
+        double disc = sqrt(fmax(fro2 * fro2 - 4.0 * det * det, 0.0));
+        double smax2 = 0.5 * (fro2 + disc), smin2 = 0.5 * (fro2 - disc);
+        *cond_out = (det == 0.0 || smin2 <= 0.0) ? INFINITY : sqrt(smax2 / smin2);
+    }
     for (int a = 0; a < 3; ++a) xout[a] = x[a];
     *rho_out = f;
     *iters_out = iters;
@@ -504,10 +514,11 @@ static void gather_patch(const grid_t *g, const float *psi, int64_t i, int64_t j
 }
 
 /* Refine the listed cells of a grid. out_x: double[3*ncell] cell-local position of the sample;
- * rho: |psi|^2 there; iters, status per sample. */
+ * rho: |psi|^2 there; iters, status per sample; cond (nullable): the condition number of the
+ * in-plane Jacobian at the sample. */
 void vxo_refine(int nx, int ny, int nz, unsigned periodic, const float *psi, int64_t ncell,
                 const uint64_t *cells, const uint16_t *cdesc, const vxo_refine_params *prm,
-                double *out_x, double *rho, int32_t *iters, int32_t *status) {
+                double *out_x, double *rho, int32_t *iters, int32_t *status, double *cond) {
     grid_t g = {{nx, ny, nz}, {(int)(periodic & 1u), (int)((periodic >> 1) & 1u), (int)((periodic >> 2) & 1u)}};
     patch_t p;
     for (int64_t s = 0; s < ncell; ++s) {
@@ -515,7 +526,7 @@ void vxo_refine(int nx, int ny, int nz, unsigned periodic, const float *psi, int
         int64_t i = n % nx, j = (n / nx) % ny, k = n / ((int64_t)nx * ny);
         gather_patch(&g, psi, i, j, k, &p);
         int it, st;
-        vxo_refine_patch(&p, cdesc[s], prm, out_x + 3 * s, rho + s, &it, &st);
+        vxo_refine_patch(&p, cdesc[s], prm, out_x + 3 * s, rho + s, &it, &st, cond ? cond + s : NULL);
         iters[s] = it;
         status[s] = st;
     }
@@ -534,7 +545,7 @@ void vxo_refine_one(const double *re, const double *im, const int *lo, const int
         p.hi[a] = hi[a];
     }
     int it, st;
-    vxo_refine_patch(&p, desc, prm, xout, rho, &it, &st);
+    vxo_refine_patch(&p, desc, prm, xout, rho, &it, &st, NULL);
     *iters = it;
     *status = st;
 }

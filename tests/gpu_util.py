@@ -54,54 +54,3 @@ def assert_winding_equal(out, W):
     assert np.array_equal(fsign, W.fsign)
     assert np.array_equal(cells, W.cells)
     assert np.array_equal(cdesc, W.cdesc)
-
-
-def window_packed(t, packed_dev, origin, size, periodic=7):
-    """The packed field of a box of a GPU-generated tangle field, next to the oracle's windings of
-    the same box computed from host-evaluated values (the generator is bit-exact with the host
-    evaluator). Returns (gpu, oracle_packed, oracle_cdesc), all of shape (bz, by, bx)."""
-    import torch
-    import oracle
-    import vxinputs
-    nx, ny, nz = t.dims
-    x0, y0, z0 = origin
-    bx, by, bz = size
-    sub = vxinputs.eval_tangle(t, (x0, y0, z0, bx + 1, by + 1, bz + 1))
-    _, packed, cdesc = oracle.winding_box(sub, t.dims, origin, periodic)
-    dev = packed_dev.device
-    zi = torch.as_tensor((z0 + np.arange(bz)) % nz, device=dev)
-    yi = torch.as_tensor((y0 + np.arange(by)) % ny, device=dev)
-    xi = torch.as_tensor((x0 + np.arange(bx)) % nx, device=dev)
-    g = packed_dev.index_select(0, zi).index_select(1, yi).index_select(2, xi).cpu().numpy()
-    return g, packed, cdesc
-
-
-def window_samples(t, samples_np, origin, size, cdesc_box, max_cells=200, seed=0):
-    """GPU samples of (up to max_cells) pierced cells of a box against the oracle refinement of the
-    same cells from host-evaluated 4x4x4 patches. samples_np: the GPU samples of the whole field
-    (any order). Returns (errors of oracle-converged cells, number of oracle-converged cells,
-    number checked)."""
-    import oracle
-    import vxinputs
-    nx, ny, nz = t.dims
-    x0, y0, z0 = origin
-    bad = oracle.NONZERO_MIN | oracle.NOT_CONVERGED | oracle.NO_FACES
-    kz, ky, kx = np.nonzero(cdesc_box)
-    rng = np.random.default_rng(seed)
-    pick = rng.permutation(len(kx))[:max_cells]
-    order = np.argsort(samples_np["cell"], kind="stable")
-    sc = samples_np["cell"][order]
-    errs, ok = [], 0
-    for p in pick:
-        i, j, k = (x0 + kx[p]) % nx, (y0 + ky[p]) % ny, (z0 + kz[p]) % nz
-        cell = i + nx * (j + ny * k)
-        at = np.searchsorted(sc, cell)
-        assert at < len(sc) and sc[at] == cell, f"cell {cell} missing from the GPU samples"
-        s = samples_np[order[at]]
-        patch = vxinputs.eval_tangle(t, (i - 1, j - 1, k - 1, 4, 4, 4)).astype(np.complex128)
-        x, rho, it, st = oracle.refine_patch(patch.real, patch.imag, int(cdesc_box[kz[p], ky[p], kx[p]]))
-        if st & bad:
-            continue
-        ok += 1
-        errs.append(np.abs(s["off"].astype(np.float64) - x).max())
-    return np.array(errs), ok, len(pick)
