@@ -79,7 +79,7 @@ def train(ex: Extractor, feat, target, n: int, init_params, epochs: int = 12, ba
             prm = AdamParams(a, 0.9, 0.999, 1e-8, conf_lambda, conf_tol)
             vx_mlp_train_step(ex.h, m, feat, target, perm[b * batch:(b + 1) * batch], batch, prm, loss)
             step += 1
-            if step % log_every == 0 or step == total:
+            if step == 1 or step % log_every == 0 or step == total:
                 l = loss.cpu().numpy()
                 hist.append((step, float(l[0]), float(l[1])))
                 _log(f"[surrogate] epoch {ep} step {step}/{total}: mse {l[0]:.3e} conf {l[1]:.3e} "
