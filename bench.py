@@ -186,6 +186,37 @@ def bench_pipeline(ex, psi, steps: int, warmup: int, cap: int, wl: str, N: int):
     }
 
 
+def bench_node_circulation(ex, wind, steps: int):
+    """Node-centred circulation (vx_node_circulation) on the benchmark's packed field: per-node byte
+    field and vortex-node list; kernel time from HIP events; algorithmic bytes 1 read + 1 written per
+    node plus 8 per listed vortex node."""
+    import torch
+
+    from paper_1911_12070_amd import KIND_NODE, dims, vx_node_circulation, vx_profile_enable, vx_profile_read
+    nz, ny, nx = wind.shape
+    node = torch.empty_like(wind)
+    lst = torch.empty(1 << 26, dtype=torch.int64, device=wind.device)
+    count = torch.zeros(1, dtype=torch.int64, device=wind.device)
+    d = dims(nx, ny, nz, 7)
+    for _ in range(2):
+        vx_node_circulation(ex.h, d, wind, count, node, lst)
+    torch.cuda.synchronize()
+    vx_profile_enable(ex.h, True)
+    for _ in range(steps):
+        vx_node_circulation(ex.h, d, wind, count, node, lst)
+    ms, k = vx_profile_read(ex.h, KIND_NODE)
+    vx_profile_enable(ex.h, False)
+    ms /= max(k, 1)
+    nv = int(count.cpu())
+    nodes = nx * ny * nz
+    alg = 2 * nodes + 8 * nv + 8
+    del node, lst
+    torch.cuda.empty_cache()
+    return {"kernel": "node_circ_k", "kernel_ms": ms, "vortex_nodes": nv, "algorithmic_bytes_per_launch": alg,
+            "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "nodes_per_s": nodes / (ms * 1e-3)}
+
+
 def calib_copy():
     """Kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
     (fill: writes 1 GiB; sum: reads 1 GiB)."""
@@ -415,6 +446,7 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
         },
     }
+    res["node_circulation"] = bench_node_circulation(ex, out["wind"], args.steps)
     del out, samples
     torch.cuda.empty_cache()
     res["pipelined"] = bench_pipeline(ex, psi, args.steps, args.warmup, cap, wl, N)

@@ -153,6 +153,25 @@ vx_status vx_winding(vx_handle *h, vx_dims dims, const void *d_psi, const vx_win
 vx_status vx_wind_config(vx_handle *h, int zchunk);
 
 /* ------------------------------------------------------------------------------------------
+ * Node-centred circulation (Sec. 2.2: three rings per grid node in the coordinate planes, the
+ * largest |C| kept, vortex node where it exceeds pi), derived from the packed face windings.
+ *
+ * The ring of node n in the plane normal to axis a is the boundary of the 2 x 2 faces around n in
+ * that plane (corners n +- e_u +- e_v); its circulation / 2 pi is the sum of those four faces'
+ * windings, e.g. C_z(n) / 2 pi = w_z(n) + w_z(n-ex) + w_z(n-ey) + w_z(n-ex-ey) (faces outside a
+ * non-periodic axis count 0). Exact integers, |C| / 2 pi <= 3.
+ *   d_wind   uint8[N] packed field of vx_winding (device, input).
+ *   d_node   uint8[N] (nullable): bits 1:0 |C| / 2 pi of the plane with the largest |C| (ties: lowest
+ *            axis), bit 2 its sign (1 = negative), bits 4:3 that plane's normal axis (0 x, 1 y, 2 z),
+ *            bit 6 = vortex node (|C| > pi), bits 5 and 7 zero; 0 where every ring has C = 0.
+ *   d_nodes  uint64[node_cap] vortex node ids (unspecified order; nullable when node_cap == 0).
+ *   d_count  int64[1]: true number of vortex nodes (zeroed by the call; overflow sets the handle's
+ *            capacity flag, see vx_sync_status).
+ * ---------------------------------------------------------------------------------------- */
+vx_status vx_node_circulation(vx_handle *h, vx_dims dims, const uint8_t *d_wind, uint8_t *d_node, uint64_t *d_nodes,
+                              int64_t node_cap, int64_t *d_count, vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
  * Core-sample refinement (Sec. 3.3.1 mean estimate, Sec. 3.3.3 density-guided minimisation).
  *
  * For listed cell i (i < min(*d_count, cap)): x0 = mean of the centres of its pierced faces;
@@ -364,7 +383,7 @@ vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char 
 /* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).
  * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate network (inference: the network
- * kernel; training: a whole step), 3 = batch, 4 = surrogate polish.
+ * kernel; training: a whole step), 3 = batch, 4 = surrogate polish, 5 = node circulation.
  * ---------------------------------------------------------------------------------------- */
 vx_status vx_profile_enable(vx_handle *h, int enable); /* enabling clears the accumulators */
 /* Sum of the recorded kernel durations (ms) and their number; synchronises the recorded events. */

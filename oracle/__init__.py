@@ -234,6 +234,45 @@ def winding_slabs(psi: np.ndarray, periodic: int = 7, threads: int = 1, slab: in
 
 
 # ----------------------------------------------------------------------------------------------
+# node-centred circulation (Sec. 2.2: rings in the three coordinate planes through a node)
+# ----------------------------------------------------------------------------------------------
+
+def node_circulation(w: np.ndarray, periodic: int = 7):
+    """Circulation / 2 pi around the ring of every node in each coordinate plane, from the face
+    windings w (nz, ny, nx, 3) of the whole-grid pass. The ring of node n in the plane normal to
+    axis a is the boundary of the four faces of orientation a that have n as a corner: the faces at
+    n, n - e_u, n - e_v and n - e_u - e_v (u, v the other two axes); the windings of faces add, so the
+    ring's circulation / 2 pi is their sum. A face that would sit at index -1 of a non-periodic axis
+    does not exist (0). Returns C (nz, ny, nx, 3) int and the node bytes: bits 1:0 |C| of the plane
+    with the largest |C| (ties: lowest axis), bit 2 its sign, bits 4:3 that axis, bit 6 = vortex node
+    (|C| / 2 pi >= 1, i.e. |C| > pi)."""
+    nz, ny, nx = w.shape[:3]
+    W = w.astype(np.int64)
+    axis_of = {0: 2, 1: 1, 2: 0}  # grid axis a -> array axis of (z, y, x)
+
+    def back(f, a):
+        """f at n - e_a (zero where n - e_a is outside a non-periodic axis)."""
+        g = np.roll(f, 1, axis=axis_of[a])
+        if not (periodic >> a) & 1:
+            sl = [slice(None)] * 3
+            sl[axis_of[a]] = 0
+            g[tuple(sl)] = 0
+        return g
+
+    C = np.zeros((nz, ny, nx, 3), np.int64)
+    for a in range(3):
+        u, v = [b for b in range(3) if b != a]
+        f = W[..., a]
+        C[..., a] = f + back(f, u) + back(f, v) + back(back(f, u), v)
+    mag = np.abs(C)
+    best = np.argmax(mag, axis=-1)  # the first maximum: ties go to the lowest axis
+    val = np.take_along_axis(C, best[..., None], axis=-1)[..., 0]
+    m = np.minimum(np.abs(val), 3)
+    node = np.where(m > 0, m | np.where(val < 0, 4, 0) | (best << 3) | 0x40, 0).astype(np.uint8)
+    return C, node
+
+
+# ----------------------------------------------------------------------------------------------
 # refinement (Sec. 3.3.1 mean estimate, Sec. 3.3.3 density-guided minimisation)
 # ----------------------------------------------------------------------------------------------
 

@@ -25,12 +25,12 @@ SAMPLE_NOT_CONVERGED = 16
 SAMPLE_NO_FACES = 32
 SAMPLE_BAD_CELL = 64
 
-KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH = 0, 1, 2, 3, 4
+KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH, KIND_NODE = 0, 1, 2, 3, 4, 5
 
 # every symbol include/vx.h declares
 EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
-           "vx_refine_noalloc",
+           "vx_refine_noalloc", "vx_node_circulation",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
@@ -130,6 +130,8 @@ def lib() -> ctypes.CDLL:
         L.vx_refine_defaults.restype = RefineParams
         L.vx_refine.argtypes = [P, Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
         L.vx_refine.restype = st
+        L.vx_node_circulation.argtypes = [P, Dims, P, P, P, ctypes.c_int64, P, P]
+        L.vx_node_circulation.restype = st
         L.vx_refine_noalloc.argtypes = [Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
         L.vx_refine_noalloc.restype = st
         L.vx_batch_create.argtypes = [P, ctypes.POINTER(Frame), i, ctypes.POINTER(RefineParams), ctypes.POINTER(P)]
@@ -257,6 +259,12 @@ def vx_refine(h, d: Dims, psi, cells, cdesc, count, out, params: RefineParams | 
     prm = params if params is not None else vx_refine_defaults()
     _check(h, lib().vx_refine(h, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(seed), _ptr(count), cap,
                               ctypes.byref(prm), _ptr(out), _stream(stream)), "vx_refine")
+
+
+def vx_node_circulation(h, d: Dims, wind, count, node=None, nodes=None, stream=None):
+    cap = int(nodes.numel()) if nodes is not None else 0
+    _check(h, lib().vx_node_circulation(h, d, _ptr(wind), _ptr(node), _ptr(nodes), cap, _ptr(count),
+                                        _stream(stream)), "vx_node_circulation")
 
 
 def vx_refine_noalloc(d: Dims, psi, cells, cdesc, count, out, params: RefineParams | None = None, seed=None,

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["vx_runtime.hip", "vx_gen.hip", "vx_wind.hip", "vx_refine.hip", "vx_batch.hip", "vx_mlp.hip"]
+SOURCES = ["vx_runtime.hip", "vx_gen.hip", "vx_wind.hip", "vx_refine.hip", "vx_batch.hip", "vx_mlp.hip",
+           "vx_node.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

@@ -12,7 +12,15 @@
 
 #include "../../include/vx.h"
 
-enum { VX_KIND_WIND = 0, VX_KIND_REFINE = 1, VX_KIND_MLP = 2, VX_KIND_BATCH = 3, VX_KIND_POLISH = 4, VX_KIND_COUNT = 5 };
+enum {
+    VX_KIND_WIND = 0,
+    VX_KIND_REFINE = 1,
+    VX_KIND_MLP = 2,
+    VX_KIND_BATCH = 3,
+    VX_KIND_POLISH = 4,
+    VX_KIND_NODE = 5,
+    VX_KIND_COUNT = 6
+};
 
 struct vx_event_pair {
     hipEvent_t start, stop;
