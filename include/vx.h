@@ -381,6 +381,38 @@ vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char 
                       vx_stream s);
 
 /* ------------------------------------------------------------------------------------------
+ * Host consumers of the lists (host memory in and out; synchronous; no device work).
+ *
+ * Dual graph of the vortex lines (Sec. 3.1 graph of vortex nodes, in dual form): the vertices are
+ * the listed pierced cells, and every pierced face joins the two cells that share it (the face's
+ * winding orients the edge by the right-hand rule, Sec. 3.4). Connected components by depth-first
+ * traversal (Sec. 3.2) started from the unvisited cell of lowest id, so component c is the one whose
+ * lowest cell id is the c-th smallest of all components' lowest ids. Class of a component from the
+ * connectivity (number of neighbour cells) of its vertices (Sec. 3.4): Type I simple open line
+ * (all <= 2, some < 2: it ends on a non-periodic boundary), Type II simple closed line (all 2),
+ * Type III complex line (some > 2). Vertices of connectivity > 2 are branch points, the
+ * reconnection candidates of Sec. 4.2 (cells with four or six pierced faces). A pierced face on a
+ * non-periodic boundary has no second cell: it is a boundary face of its cell.
+ *   h_cells, h_cell_desc  the pierced cells and their descriptors (as vx_winding lists them, any
+ *                         order, n entries; every pierced face's other cell must be listed)
+ *   h_comp    int64[n]  component of each input cell
+ *   h_degree  int32[n]  (nullable) its connectivity
+ *   h_comp_type int32[n] (nullable) type (1, 2, 3) of component c at index c (at most n components)
+ * VX_ERR_INVALID for a duplicate cell, a cell id outside the grid, or a pierced face whose other cell
+ * is not listed (stats->bad_input then gives the input position). */
+typedef struct {
+    int64_t nvert;      /* vertices (listed cells) */
+    int64_t nedge;      /* edges: pierced faces shared by two listed cells */
+    int64_t nboundary;  /* pierced faces on a non-periodic boundary */
+    int64_t ncomp;      /* connected components */
+    int64_t ntype[3];   /* components of Type I, II, III */
+    int64_t nbranch;    /* vertices of connectivity > 2 */
+    int64_t bad_input;  /* input position of an invalid entry (-1 if none) */
+} vx_graph_stats;
+vx_status vx_graph_lines(vx_dims dims, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n,
+                         int64_t *h_comp, int32_t *h_degree, int32_t *h_comp_type, vx_graph_stats *stats);
+
+/* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).
  * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate network (inference: the network
  * kernel; training: a whole step), 3 = batch, 4 = surrogate polish, 5 = node circulation.

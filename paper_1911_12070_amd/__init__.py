@@ -30,7 +30,7 @@ KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH, KIND_NODE = 0, 1, 2, 
 # every symbol include/vx.h declares
 EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
-           "vx_refine_noalloc", "vx_node_circulation",
+           "vx_refine_noalloc", "vx_node_circulation", "vx_graph_lines",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
@@ -89,6 +89,12 @@ class AdamParams(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in ("lr", "beta1", "beta2", "eps", "conf_lambda", "conf_tol")]
 
 
+class GraphStats(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int64), ("nedge", ctypes.c_int64), ("nboundary", ctypes.c_int64),
+                ("ncomp", ctypes.c_int64), ("ntype", ctypes.c_int64 * 3), ("nbranch", ctypes.c_int64),
+                ("bad_input", ctypes.c_int64)]
+
+
 class Frame(ctypes.Structure):
     _fields_ = [("dims", Dims), ("d_psi", ctypes.c_void_p), ("out", WindingOut), ("d_samples", ctypes.c_void_p),
                 ("sample_cap", ctypes.c_int64)]
@@ -130,6 +136,8 @@ def lib() -> ctypes.CDLL:
         L.vx_refine_defaults.restype = RefineParams
         L.vx_refine.argtypes = [P, Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
         L.vx_refine.restype = st
+        L.vx_graph_lines.argtypes = [Dims, P, P, ctypes.c_int64, P, P, P, ctypes.POINTER(GraphStats)]
+        L.vx_graph_lines.restype = st
         L.vx_node_circulation.argtypes = [P, Dims, P, P, P, ctypes.c_int64, P, P]
         L.vx_node_circulation.restype = st
         L.vx_refine_noalloc.argtypes = [Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
@@ -259,6 +267,26 @@ def vx_refine(h, d: Dims, psi, cells, cdesc, count, out, params: RefineParams | 
     prm = params if params is not None else vx_refine_defaults()
     _check(h, lib().vx_refine(h, d, _ptr(psi), _ptr(cells), _ptr(cdesc), _ptr(seed), _ptr(count), cap,
                               ctypes.byref(prm), _ptr(out), _stream(stream)), "vx_refine")
+
+
+def vx_graph_lines(d: Dims, cells, cdesc):
+    """Dual graph of host lists (numpy uint64 cells, uint16 descriptors): (comp int64[n], degree
+    int32[n], comp_type int32[ncomp], stats dict)."""
+    import numpy as np
+    cells = np.ascontiguousarray(cells, np.uint64)
+    cdesc = np.ascontiguousarray(cdesc, np.uint16)
+    n = len(cells)
+    comp = np.empty(n, np.int64)
+    deg = np.empty(n, np.int32)
+    ctype = np.empty(max(n, 1), np.int32)
+    st = GraphStats()
+    status = lib().vx_graph_lines(d, cells.ctypes.data, cdesc.ctypes.data, n, comp.ctypes.data, deg.ctypes.data,
+                                  ctype.ctypes.data, ctypes.byref(st))
+    if status != VX_OK:
+        raise VxError(status, f"vx_graph_lines: {lib().vx_status_str(status).decode()} (input {st.bad_input})")
+    stats = {"nvert": st.nvert, "nedge": st.nedge, "nboundary": st.nboundary, "ncomp": st.ncomp,
+             "ntype": list(st.ntype), "nbranch": st.nbranch}
+    return comp, deg, ctype[:st.ncomp].copy(), stats
 
 
 def vx_node_circulation(h, d: Dims, wind, count, node=None, nodes=None, stream=None):

@@ -30,6 +30,11 @@ PER_FILE = {
 }
 
 
+# host-only C++ (the consumers of the lists: graph, sampling, curves), built with the host compiler
+CPP_SOURCES = ["vx_graph.cpp"]
+CPP_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-fno-fast-math", "-ffp-contract=off"]
+
+
 def _hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if c and (os.path.isabs(c) and os.path.exists(c) or not os.path.isabs(c)):
@@ -51,8 +56,18 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(one, SOURCES))
+    def one_cpp(src):
+        obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        cmd = [os.environ.get("CXX", "g++"), *CPP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"host compiler failed for {src}:\n{r.stderr}")
+        if verbose and r.stderr.strip():
+            print(r.stderr, file=sys.stderr)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + len(CPP_SOURCES))) as ex:
+        objs = list(ex.map(one, SOURCES)) + list(ex.map(one_cpp, CPP_SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
