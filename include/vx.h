@@ -412,6 +412,36 @@ typedef struct {
 vx_status vx_graph_lines(vx_dims dims, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n,
                          int64_t *h_comp, int32_t *h_degree, int32_t *h_comp_type, vx_graph_stats *stats);
 
+/* Sample points by box means and iterative graph reduction (Sec. 3.3.1 candidate sample points,
+ * Sec. 3.3.2 graph reduction), on the dual graph above. Each vertex (pierced cell) stands at its
+ * first estimate: min corner + mean of its pierced-face centres. One pass: take the unprocessed
+ * vertex of lowest id (or the seed chosen below); collect, by depth-first traversal from it, the
+ * connected unprocessed vertices whose position lies in the box of side box_k cells centred on it
+ * (|dx|, |dy|, |dz| <= box_k / 2, minimum image on periodic axes); they collapse into one new node at
+ * their mean position (sums in ascending vertex order, relative to the first vertex, wrapped into
+ * the grid); the next vertex is the lowest-id unprocessed neighbour of the collapsed ones, else the
+ * lowest unprocessed vertex. The new nodes, numbered in creation order, are joined where any of their
+ * members were. Passes repeat on the reduced graph until one merges nothing (the positions have
+ * converged) or max_passes is reached. Host memory; synchronous.
+ *   vx_reduce         builds the reduced graph (*out, freed by vx_reduced_destroy); VX_ERR_INVALID
+ *                     for lists vx_graph_lines rejects, box_k outside 1..64, max_passes outside 1..64
+ *   vx_reduced_info   number of nodes, of edges, passes run
+ *   vx_reduced_get    (each nullable) h_pos double[nnode][3] node positions; h_edges int64[nedge][2]
+ *                     (u < v, ascending); h_members int64[nnode] pierced cells merged into each node;
+ *                     h_comp int64[nnode] component of the dual graph it came from
+ *   vx_reduced_seeds  the refinement inputs of the nodes (for vx_refine's caller seeds): the cell that
+ *                     holds each node (clamped to the cells of an open axis), that cell's descriptor
+ *                     if it is in the given pierced list (else 0), and the node's offset from the
+ *                     cell's min corner (FP32, cell-local as vx_refine takes it) */
+typedef struct vx_reduced vx_reduced;
+vx_status vx_reduce(vx_dims dims, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n, int box_k,
+                    int max_passes, vx_reduced **out);
+vx_status vx_reduced_info(const vx_reduced *r, int64_t *nnode, int64_t *nedge, int32_t *passes);
+vx_status vx_reduced_get(const vx_reduced *r, double *h_pos, int64_t *h_edges, int64_t *h_members, int64_t *h_comp);
+vx_status vx_reduced_seeds(const vx_reduced *r, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n,
+                           uint64_t *h_seed_cell, uint16_t *h_seed_desc, float *h_seed_off);
+vx_status vx_reduced_destroy(vx_reduced *r);
+
 /* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).
  * kind: 0 = winding kernel, 1 = refinement kernel, 2 = surrogate network (inference: the network

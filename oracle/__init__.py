@@ -87,7 +87,7 @@ def _load():
         lib.vxo_winding.restype = None
         lib.vxo_winding_box.argtypes = [i, i, i, ctypes.c_uint, i, i, i, i, i, i, P, P, P, P]
         lib.vxo_winding_box.restype = None
-        lib.vxo_refine.argtypes = [i, i, i, ctypes.c_uint, P, ctypes.c_int64, P, P,
+        lib.vxo_refine.argtypes = [i, i, i, ctypes.c_uint, P, ctypes.c_int64, P, P, P,
                                    ctypes.POINTER(_RefineParams), P, P, P, P, P]
         lib.vxo_refine.restype = None
         lib.vxo_refine_one.argtypes = [P, P, P, P, ctypes.c_uint, ctypes.POINTER(_RefineParams),
@@ -286,9 +286,10 @@ class Samples:
 
 
 def refine(psi: np.ndarray, cells: np.ndarray, cdesc: np.ndarray, params: RefineParams | None = None,
-           periodic: int = 7, threads: int = 1) -> Samples:
+           periodic: int = 7, threads: int = 1, seeds: np.ndarray | None = None) -> Samples:
     """Refine the listed cells; with threads > 1 the list is cut into contiguous chunks refined in
-    host threads (each sample is independent, so the results are the same)."""
+    host threads (each sample is independent, so the results are the same). seeds (n, 3), cell-local,
+    replace the face-centre first estimates as starting points."""
     params = params or RefineParams()
     nz, ny, nx = psi.shape
     f = _f32pairs(psi)
@@ -300,12 +301,14 @@ def refine(psi: np.ndarray, cells: np.ndarray, cdesc: np.ndarray, params: Refine
     iters = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
     cond = np.zeros(n, np.float64)
+    sd = np.ascontiguousarray(seeds, np.float64).reshape(n, 3) if seeds is not None else None
     pr = params.c()
     lib = _load()
 
     def run(a, b):
         if b > a:
-            lib.vxo_refine(nx, ny, nz, periodic, _p(f), b - a, _p(cells[a:]), _p(cdesc[a:]), ctypes.byref(pr),
+            lib.vxo_refine(nx, ny, nz, periodic, _p(f), b - a, _p(cells[a:]), _p(cdesc[a:]),
+                           _p(sd[a:]) if sd is not None else None, ctypes.byref(pr),
                            _p(x[a:]), _p(rho[a:]), _p(iters[a:]), _p(status[a:]), _p(cond[a:]))
 
     if threads <= 1 or n < 2 * threads:

@@ -9,10 +9,16 @@ plainly in Python from the paper's description.
   classes      Sec. 3.4: Type I (connectivity <= 2 everywhere, some vertex below 2), Type II (2
                everywhere), Type III (some vertex above 2); branch points: connectivity > 2
                (Sec. 4.2 reconnection events).
+  samples      Sec. 3.3.1 / 3.3.2: the candidate sample around a vertex is the mean position of the
+               connected sub-graph inside a box of side k around it; the sub-graph collapses into one
+               node; the next vertex is an unprocessed neighbour of the collapsed ones; passes repeat
+               on the reduced graph until nothing merges.
 
 It shares no code with the GPU library and never imports it.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -92,3 +98,111 @@ def graph_lines(dims, periodic, cells, cdesc):
     stats = {"nvert": len(cells), "nedge": int(deg.sum()) // 2, "nboundary": int(sum(nbound)), "ncomp": nc,
              "ntype": [int((types == t).sum()) for t in (1, 2, 3)], "nbranch": int((deg > 2).sum())}
     return comp, deg.astype(np.int32), types, stats
+
+
+# ----------------------------------------------------------------------------------------------
+# sample points by box means and iterative graph reduction (Sec. 3.3.1, 3.3.2)
+# ----------------------------------------------------------------------------------------------
+
+def first_estimate_point(dims, cell: int, desc: int):
+    """Min corner of the cell plus the mean of its pierced-face centres (the mean-position estimator
+    of Sec. 3.3.1 with a one-cell box)."""
+    nx, ny, nz = dims
+    co = [cell % nx, (cell // nx) % ny, cell // (nx * ny)]
+    s = [0.0, 0.0, 0.0]
+    k = 0
+    for f, w in enumerate(decode(desc)):
+        if w == 0:
+            continue
+        for a in range(3):
+            s[a] += float(f % 2) if a == f // 2 else 0.5
+        k += 1
+    return [co[a] + (s[a] / k if k else 0.5) for a in range(3)]
+
+
+def _disp(dims, periodic, a, b):
+    """b - a with the minimum image on periodic axes (ties of the rounding to even)."""
+    out = []
+    for q in range(3):
+        t = b[q] - a[q]
+        if (periodic >> q) & 1:
+            t -= dims[q] * round(t / dims[q])
+        out.append(t)
+    return out
+
+
+def _wrap(dims, periodic, x, q):
+    if (periodic >> q) & 1:
+        return x - dims[q] * math.floor(x / dims[q])
+    return x
+
+
+def reduce_once(dims, periodic, pos, adj, members, comp, half):
+    """One pass of the reduction. pos: list of [x, y, z]; adj: list of sets of neighbour ids.
+    Returns the reduced (pos, adj, members, comp)."""
+    n = len(pos)
+    done = [False] * n
+    owner = [-1] * n
+    rpos, rmem, rcomp = [], [], []
+    seed = None
+    while True:
+        if seed is None:
+            rest = [v for v in range(n) if not done[v]]
+            if not rest:
+                break
+            v = rest[0]
+        else:
+            v = seed
+        # the connected unprocessed vertices inside the box around v (depth-first traversal)
+        sub = []
+        done[v] = True
+        stack = [v]
+        while stack:
+            u = stack.pop()
+            sub.append(u)
+            for w in adj[u]:
+                if not done[w] and all(abs(t) <= half for t in _disp(dims, periodic, pos[v], pos[w])):
+                    done[w] = True
+                    stack.append(w)
+        sub.sort()
+        acc = [0.0, 0.0, 0.0]
+        for u in sub:
+            d = _disp(dims, periodic, pos[v], pos[u])
+            for q in range(3):
+                acc[q] += d[q]
+        rid = len(rpos)
+        rpos.append([_wrap(dims, periodic, pos[v][q] + acc[q] / len(sub), q) for q in range(3)])
+        rmem.append(sum(members[u] for u in sub))
+        rcomp.append(comp[v])
+        for u in sub:
+            owner[u] = rid
+        cand = [w for u in sub for w in adj[u] if not done[w]]
+        seed = min(cand) if cand else None
+    radj = [set() for _ in rpos]
+    for u in range(n):
+        for w in adj[u]:
+            if owner[u] != owner[w]:
+                radj[owner[u]].add(owner[w])
+    return rpos, radj, rmem, rcomp
+
+
+def reduce_graph(dims, periodic, cells, cdesc, box_k, max_passes):
+    """The reduced graph: (pos [m][3], sorted edge list [(u, v), u < v], members, comp, passes)."""
+    order = sorted(range(len(cells)), key=lambda i: int(cells[i]))
+    scells = [int(cells[i]) for i in order]
+    sdesc = [int(cdesc[i]) for i in order]
+    adj_in, _ = dual_graph(dims, periodic, scells, sdesc)
+    comp, _ = components(scells, adj_in)
+    pos = [first_estimate_point(dims, c, d) for c, d in zip(scells, sdesc)]
+    adj = [set(j for j, _ in a if j != i) for i, a in enumerate(adj_in)]
+    members = [1] * len(pos)
+    comp = comp.tolist()
+    passes = 0
+    for _ in range(max_passes):
+        n0 = len(pos)
+        pos, adj, members, comp = reduce_once(dims, periodic, pos, adj, members, comp, 0.5 * box_k)
+        passes += 1
+        if len(pos) == n0:
+            break
+    edges = sorted((u, w) for u in range(len(pos)) for w in adj[u] if u < w)
+    return np.array(pos, np.float64).reshape(-1, 3), edges, members, comp, passes

@@ -318,8 +318,8 @@ static int dec2(unsigned desc, int f) {
  *     newton_tol.
  *  Trial points outside the patch count as rejected trials (status BOUNDARY).
  */
-void vxo_refine_patch(const patch_t *p, unsigned desc, const vxo_refine_params *prm, double xout[3],
-                      double *rho_out, int *iters_out, int *status_out, double *cond_out) {
+void vxo_refine_patch(const patch_t *p, unsigned desc, const double *seed, const vxo_refine_params *prm,
+                      double xout[3], double *rho_out, int *iters_out, int *status_out, double *cond_out) {
     static const double ctr[6][3] = {{0, .5, .5}, {1, .5, .5}, {.5, 0, .5},
                                      {.5, 1, .5}, {.5, .5, 0}, {.5, .5, 1}};
     int status = 0, npierced = 0;
@@ -336,6 +336,9 @@ void vxo_refine_patch(const patch_t *p, unsigned desc, const vxo_refine_params *
         for (int a = 0; a < 3; ++a) x0[a] /= npierced;
     }
     if (npierced >= 4) status |= ST_MULTI;
+    /* a caller's seed (a sample point of the box reduction, Sec. 3.3.2) replaces the estimate */
+    if (seed)
+        for (int a = 0; a < 3; ++a) x0[a] = seed[a];
 
     double vr, vi, gr[3], gi[3];
     trilerp(p, x0, &vr, &vi, gr, gi);
@@ -515,9 +518,10 @@ static void gather_patch(const grid_t *g, const float *psi, int64_t i, int64_t j
 
 /* Refine the listed cells of a grid. out_x: double[3*ncell] cell-local position of the sample;
  * rho: |psi|^2 there; iters, status per sample; cond (nullable): the condition number of the
- * in-plane Jacobian at the sample. */
+ * in-plane Jacobian at the sample. seeds (nullable, double[3*ncell], cell-local): starting points that
+ * replace the face-centre estimate. */
 void vxo_refine(int nx, int ny, int nz, unsigned periodic, const float *psi, int64_t ncell,
-                const uint64_t *cells, const uint16_t *cdesc, const vxo_refine_params *prm,
+                const uint64_t *cells, const uint16_t *cdesc, const double *seeds, const vxo_refine_params *prm,
                 double *out_x, double *rho, int32_t *iters, int32_t *status, double *cond) {
     grid_t g = {{nx, ny, nz}, {(int)(periodic & 1u), (int)((periodic >> 1) & 1u), (int)((periodic >> 2) & 1u)}};
     patch_t p;
@@ -526,7 +530,8 @@ void vxo_refine(int nx, int ny, int nz, unsigned periodic, const float *psi, int
         int64_t i = n % nx, j = (n / nx) % ny, k = n / ((int64_t)nx * ny);
         gather_patch(&g, psi, i, j, k, &p);
         int it, st;
-        vxo_refine_patch(&p, cdesc[s], prm, out_x + 3 * s, rho + s, &it, &st, cond ? cond + s : NULL);
+        vxo_refine_patch(&p, cdesc[s], seeds ? seeds + 3 * s : NULL, prm, out_x + 3 * s, rho + s, &it, &st,
+                         cond ? cond + s : NULL);
         iters[s] = it;
         status[s] = st;
     }
@@ -545,7 +550,7 @@ void vxo_refine_one(const double *re, const double *im, const int *lo, const int
         p.hi[a] = hi[a];
     }
     int it, st;
-    vxo_refine_patch(&p, desc, prm, xout, rho, &it, &st, NULL);
+    vxo_refine_patch(&p, desc, NULL, prm, xout, rho, &it, &st, NULL);
     *iters = it;
     *status = st;
 }

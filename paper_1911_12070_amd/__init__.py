@@ -31,6 +31,7 @@ KIND_WIND, KIND_REFINE, KIND_MLP, KIND_BATCH, KIND_POLISH, KIND_NODE = 0, 1, 2, 
 EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status_str", "vx_last_error", "vx_gen_tangle",
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
            "vx_refine_noalloc", "vx_node_circulation", "vx_graph_lines",
+           "vx_reduce", "vx_reduced_info", "vx_reduced_get", "vx_reduced_seeds", "vx_reduced_destroy",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
@@ -138,6 +139,14 @@ def lib() -> ctypes.CDLL:
         L.vx_refine.restype = st
         L.vx_graph_lines.argtypes = [Dims, P, P, ctypes.c_int64, P, P, P, ctypes.POINTER(GraphStats)]
         L.vx_graph_lines.restype = st
+        L.vx_reduce.argtypes = [Dims, P, P, ctypes.c_int64, i, i, ctypes.POINTER(P)]
+        L.vx_reduced_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32)]
+        L.vx_reduced_get.argtypes = [P, P, P, P, P]
+        L.vx_reduced_seeds.argtypes = [P, P, P, ctypes.c_int64, P, P, P]
+        L.vx_reduced_destroy.argtypes = [P]
+        for name in ("vx_reduce", "vx_reduced_info", "vx_reduced_get", "vx_reduced_seeds", "vx_reduced_destroy"):
+            getattr(L, name).restype = st
         L.vx_node_circulation.argtypes = [P, Dims, P, P, P, ctypes.c_int64, P, P]
         L.vx_node_circulation.restype = st
         L.vx_refine_noalloc.argtypes = [Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
@@ -287,6 +296,39 @@ def vx_graph_lines(d: Dims, cells, cdesc):
     stats = {"nvert": st.nvert, "nedge": st.nedge, "nboundary": st.nboundary, "ncomp": st.ncomp,
              "ntype": list(st.ntype), "nbranch": st.nbranch}
     return comp, deg, ctype[:st.ncomp].copy(), stats
+
+
+def vx_reduce(d: Dims, cells, cdesc, box_k: int, max_passes: int = 5):
+    """Reduced sample graph of host lists: dict with pos (m, 3), edges (e, 2), members, comp, passes,
+    and the refinement seeds (seed_cell, seed_desc, seed_off) of the nodes."""
+    import numpy as np
+    cells = np.ascontiguousarray(cells, np.uint64)
+    cdesc = np.ascontiguousarray(cdesc, np.uint16)
+    r = ctypes.c_void_p()
+    L = lib()
+    st = L.vx_reduce(d, cells.ctypes.data, cdesc.ctypes.data, len(cells), int(box_k), int(max_passes), ctypes.byref(r))
+    if st != VX_OK:
+        raise VxError(st, f"vx_reduce: {L.vx_status_str(st).decode()}")
+    try:
+        nn, ne, npass = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        L.vx_reduced_info(r, ctypes.byref(nn), ctypes.byref(ne), ctypes.byref(npass))
+        m, e = nn.value, ne.value
+        pos = np.empty((m, 3), np.float64)
+        edges = np.empty((e, 2), np.int64)
+        members = np.empty(m, np.int64)
+        comp = np.empty(m, np.int64)
+        L.vx_reduced_get(r, pos.ctypes.data, edges.ctypes.data, members.ctypes.data, comp.ctypes.data)
+        seed_cell = np.empty(m, np.uint64)
+        seed_desc = np.empty(m, np.uint16)
+        seed_off = np.empty((m, 3), np.float32)
+        st = L.vx_reduced_seeds(r, cells.ctypes.data, cdesc.ctypes.data, len(cells), seed_cell.ctypes.data,
+                                seed_desc.ctypes.data, seed_off.ctypes.data)
+        if st != VX_OK:
+            raise VxError(st, "vx_reduced_seeds")
+    finally:
+        L.vx_reduced_destroy(r)
+    return {"pos": pos, "edges": edges, "members": members, "comp": comp, "passes": npass.value,
+            "seed_cell": seed_cell, "seed_desc": seed_desc, "seed_off": seed_off}
 
 
 def vx_node_circulation(h, d: Dims, wind, count, node=None, nodes=None, stream=None):

@@ -8,9 +8,17 @@
 //     most 2, some below 2), Type II (simple closed: every vertex of connectivity 2), Type III
 //     (complex: some vertex of connectivity above 2); vertices of connectivity above 2 are the
 //     branch points, the reconnection candidates of Sec. 4.2.
+//   * sample points by box means and iterative graph reduction (Sec. 3.3.1, 3.3.2): the candidate
+//     sample around a vertex is the mean position of the connected sub-graph inside a box of side
+//     k cells centred on it; that sub-graph collapses into one node of a reduced graph; the next
+//     vertex is an unprocessed neighbour of the collapsed ones; passes repeat on the reduced graph
+//     until nothing merges (positions converged) or a pass limit is reached.
 // A face on a non-periodic grid boundary has no second cell: it is counted as a boundary face of its
 // cell, and that cell's connectivity is its number of neighbour cells.
+// Every floating-point sum runs in ascending vertex order and nothing is contracted, so the results
+// do not depend on traversal order and are reproducible bit for bit.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -133,9 +141,141 @@ inline void classify(const Dual &g, const std::vector<int64_t> &comp, int64_t nc
     for (int64_t c = 0; c < nc; ++c) type[c] = maxdeg[c] > 2 ? 3 : (mindeg[c] == 2 ? 2 : 1);
 }
 
+// ------------------------------------------------------------------------------------------------
+// Sample points (Sec. 3.3.1, 3.3.2)
+
+// Position of a pierced cell's first estimate: its min corner plus the mean of its pierced-face
+// centres (the face normal to -e_a has centre 1/2 on the other axes and 0 on a, +e_a 1 on a).
+inline void cell_point(const vx_dims &d, uint64_t c, uint32_t desc, double p[3]) {
+    const uint64_t co[3] = {c % (uint64_t)d.nx, (c / (uint64_t)d.nx) % (uint64_t)d.ny,
+                            c / ((uint64_t)d.nx * (uint64_t)d.ny)};
+    double s[3] = {0.0, 0.0, 0.0};
+    int np = 0;
+    for (int f = 0; f < 6; ++f) {
+        if (dec2(desc, f) == 0) continue;
+        for (int a = 0; a < 3; ++a) s[a] += a == (f >> 1) ? (double)(f & 1) : 0.5;
+        ++np;
+    }
+    for (int a = 0; a < 3; ++a) p[a] = (double)co[a] + (np ? s[a] / (double)np : 0.5);
+}
+
+struct Geom {
+    double n[3];
+    int per[3];
+    // displacement b - a, minimum image on periodic axes
+    void disp(const double *a, const double *b, double *o) const {
+        for (int q = 0; q < 3; ++q) {
+            double t = b[q] - a[q];
+            if (per[q]) t -= n[q] * std::nearbyint(t / n[q]);
+            o[q] = t;
+        }
+    }
+    // position wrapped into [0, n) on periodic axes
+    double wrap(double x, int q) const { return per[q] ? x - n[q] * std::floor(x / n[q]) : x; }
+};
+
+// A graph of points: positions, undirected adjacency (CSR, duplicates removed, no self loops).
+struct PGraph {
+    int64_t n = 0;
+    std::vector<double> pos;      // [n][3]
+    std::vector<int64_t> start;   // [n+1]
+    std::vector<int64_t> nbr;
+    std::vector<int64_t> members; // original vertices merged into each node
+    std::vector<int64_t> comp;    // component (of the original graph) of each node
+};
+
+inline void csr_from_pairs(int64_t n, std::vector<std::pair<int64_t, int64_t>> &pairs, PGraph &g) {
+    std::vector<std::pair<int64_t, int64_t>> both;
+    both.reserve(2 * pairs.size());
+    for (auto &e : pairs)
+        if (e.first != e.second) {
+            both.emplace_back(e.first, e.second);
+            both.emplace_back(e.second, e.first);
+        }
+    std::sort(both.begin(), both.end());
+    both.erase(std::unique(both.begin(), both.end()), both.end());
+    g.start.assign(n + 1, 0);
+    g.nbr.resize(both.size());
+    for (size_t i = 0; i < both.size(); ++i) {
+        ++g.start[both[i].first + 1];
+        g.nbr[i] = both[i].second;
+    }
+    for (int64_t v = 0; v < n; ++v) g.start[v + 1] += g.start[v];
+}
+
+// One reduction pass; returns the reduced graph.
+inline PGraph reduce_pass(const PGraph &g, const Geom &geo, double half) {
+    PGraph r;
+    std::vector<char> done(g.n, 0);
+    std::vector<int64_t> owner(g.n, -1), stack, sub, cand;
+    int64_t lowest = 0, seed = -1;
+    for (;;) {
+        int64_t v = seed;
+        if (v < 0) {
+            while (lowest < g.n && done[lowest]) ++lowest;
+            if (lowest == g.n) break;
+            v = lowest;
+        }
+        // connected sub-graph of unprocessed vertices inside the box around v (depth-first)
+        const double *pv = &g.pos[3 * v];
+        sub.clear();
+        stack.assign(1, v);
+        done[v] = 1;
+        while (!stack.empty()) {
+            const int64_t u = stack.back();
+            stack.pop_back();
+            sub.push_back(u);
+            for (int64_t e = g.start[u]; e < g.start[u + 1]; ++e) {
+                const int64_t w = g.nbr[e];
+                if (done[w]) continue;
+                double dd[3];
+                geo.disp(pv, &g.pos[3 * w], dd);
+                if (std::fabs(dd[0]) <= half && std::fabs(dd[1]) <= half && std::fabs(dd[2]) <= half) {
+                    done[w] = 1;
+                    stack.push_back(w);
+                }
+            }
+        }
+        std::sort(sub.begin(), sub.end());
+        // the mean position, summed in ascending vertex order relative to v
+        double acc[3] = {0.0, 0.0, 0.0};
+        int64_t nmem = 0;
+        for (int64_t u : sub) {
+            double dd[3];
+            geo.disp(pv, &g.pos[3 * u], dd);
+            for (int q = 0; q < 3; ++q) acc[q] += dd[q];
+            nmem += g.members[u];
+        }
+        const int64_t id = r.n++;
+        for (int q = 0; q < 3; ++q) r.pos.push_back(geo.wrap(pv[q] + acc[q] / (double)sub.size(), q));
+        r.members.push_back(nmem);
+        r.comp.push_back(g.comp[v]);
+        for (int64_t u : sub) owner[u] = id;
+        // next: the lowest unprocessed neighbour of the collapsed vertices
+        seed = -1;
+        for (int64_t u : sub)
+            for (int64_t e = g.start[u]; e < g.start[u + 1]; ++e) {
+                const int64_t w = g.nbr[e];
+                if (!done[w] && (seed < 0 || w < seed)) seed = w;
+            }
+    }
+    std::vector<std::pair<int64_t, int64_t>> pairs;
+    for (int64_t u = 0; u < g.n; ++u)
+        for (int64_t e = g.start[u]; e < g.start[u + 1]; ++e)
+            if (u < g.nbr[e]) pairs.emplace_back(owner[u], owner[g.nbr[e]]);
+    csr_from_pairs(r.n, pairs, r);
+    return r;
+}
+
 }  // namespace vxg
 
 using namespace vxg;
+
+struct vx_reduced {
+    vx_dims dims{};
+    int passes = 0;
+    PGraph g;
+};
 
 extern "C" vx_status vx_graph_lines(vx_dims dims, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n,
                                     int64_t *h_comp, int32_t *h_degree, int32_t *h_comp_type, vx_graph_stats *stats) {
@@ -172,4 +312,115 @@ extern "C" vx_status vx_graph_lines(vx_dims dims, const uint64_t *h_cells, const
     } catch (const std::bad_alloc &) {
         return VX_ERR_NOMEM;
     }
+}
+
+extern "C" vx_status vx_reduce(vx_dims dims, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n, int box_k,
+                               int max_passes, vx_reduced **out) {
+    if (!out) return VX_ERR_INVALID;
+    *out = nullptr;
+    if (n < 0 || (n > 0 && (!h_cells || !h_cell_desc)) || box_k < 1 || box_k > 64 || max_passes < 1 || max_passes > 64)
+        return VX_ERR_INVALID;
+    if (dims.nx < 1 || dims.ny < 1 || dims.nz < 1 || dims.periodic > 7u) return VX_ERR_INVALID;
+    try {
+        Dual dg;
+        int64_t bad = -1;
+        if (vx_status st = build_dual(dims, h_cells, h_cell_desc, n, dg, &bad)) return st;
+        std::vector<int64_t> comp;
+        components(dg, comp);
+        PGraph g;
+        g.n = n;
+        g.pos.resize(3 * (size_t)n);
+        for (int64_t v = 0; v < n; ++v) cell_point(dims, dg.cell[v], dg.desc[v], &g.pos[3 * v]);
+        g.members.assign(n, 1);
+        g.comp = comp;
+        std::vector<std::pair<int64_t, int64_t>> pairs;
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t e = dg.start[v]; e < dg.start[v + 1]; ++e)
+                if (v < dg.nbr[e]) pairs.emplace_back(v, dg.nbr[e]);
+        csr_from_pairs(n, pairs, g);
+        Geom geo{{(double)dims.nx, (double)dims.ny, (double)dims.nz},
+                 {(int)(dims.periodic & 1u), (int)((dims.periodic >> 1) & 1u), (int)((dims.periodic >> 2) & 1u)}};
+        vx_reduced *r = new vx_reduced();
+        r->dims = dims;
+        for (int p = 0; p < max_passes; ++p) {
+            PGraph next = reduce_pass(g, geo, 0.5 * box_k);
+            const bool merged = next.n < g.n;
+            g = std::move(next);
+            ++r->passes;
+            if (!merged) break;
+        }
+        r->g = std::move(g);
+        *out = r;
+        return VX_OK;
+    } catch (const std::bad_alloc &) {
+        return VX_ERR_NOMEM;
+    }
+}
+
+extern "C" vx_status vx_reduced_info(const vx_reduced *r, int64_t *nnode, int64_t *nedge, int32_t *passes) {
+    if (!r) return VX_ERR_INVALID;
+    if (nnode) *nnode = r->g.n;
+    if (nedge) *nedge = (int64_t)r->g.nbr.size() / 2;
+    if (passes) *passes = r->passes;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_reduced_get(const vx_reduced *r, double *h_pos, int64_t *h_edges, int64_t *h_members,
+                                    int64_t *h_comp) {
+    if (!r) return VX_ERR_INVALID;
+    const PGraph &g = r->g;
+    if (h_pos) std::memcpy(h_pos, g.pos.data(), g.pos.size() * sizeof(double));
+    if (h_edges) {
+        int64_t k = 0;
+        for (int64_t u = 0; u < g.n; ++u)
+            for (int64_t e = g.start[u]; e < g.start[u + 1]; ++e)
+                if (u < g.nbr[e]) {
+                    h_edges[2 * k] = u;
+                    h_edges[2 * k + 1] = g.nbr[e];
+                    ++k;
+                }
+    }
+    if (h_members) std::memcpy(h_members, g.members.data(), g.members.size() * sizeof(int64_t));
+    if (h_comp) std::memcpy(h_comp, g.comp.data(), g.comp.size() * sizeof(int64_t));
+    return VX_OK;
+}
+
+extern "C" vx_status vx_reduced_seeds(const vx_reduced *r, const uint64_t *h_cells, const uint16_t *h_cell_desc,
+                                      int64_t n, uint64_t *h_seed_cell, uint16_t *h_seed_desc, float *h_seed_off) {
+    if (!r || !h_seed_cell || !h_seed_desc || !h_seed_off || n < 0 || (n > 0 && (!h_cells || !h_cell_desc)))
+        return VX_ERR_INVALID;
+    try {
+        const vx_dims &d = r->dims;
+        std::vector<std::pair<uint64_t, uint16_t>> listed(n);
+        for (int64_t i = 0; i < n; ++i) listed[i] = {h_cells[i], h_cell_desc[i]};
+        std::sort(listed.begin(), listed.end());
+        const int64_t dim[3] = {d.nx, d.ny, d.nz};
+        for (int64_t v = 0; v < r->g.n; ++v) {
+            int64_t c[3];
+            for (int q = 0; q < 3; ++q) {
+                const double x = r->g.pos[3 * v + q], fl = std::floor(x);
+                double off;
+                if ((d.periodic >> q) & 1u) {  // the cell that holds x, wrapped
+                    c[q] = (((int64_t)fl % dim[q]) + dim[q]) % dim[q];
+                    off = x - fl;
+                } else {  // cells of an open axis: min corner 0 .. n - 2
+                    c[q] = std::min<int64_t>(std::max<int64_t>((int64_t)fl, 0), std::max<int64_t>(dim[q] - 2, 0));
+                    off = x - (double)c[q];
+                }
+                h_seed_off[3 * v + q] = (float)off;
+            }
+            const uint64_t id = (uint64_t)c[0] + (uint64_t)d.nx * ((uint64_t)c[1] + (uint64_t)d.ny * (uint64_t)c[2]);
+            h_seed_cell[v] = id;
+            const auto it = std::lower_bound(listed.begin(), listed.end(), std::make_pair(id, (uint16_t)0));
+            h_seed_desc[v] = (it != listed.end() && it->first == id) ? it->second : 0;
+        }
+        return VX_OK;
+    } catch (const std::bad_alloc &) {
+        return VX_ERR_NOMEM;
+    }
+}
+
+extern "C" vx_status vx_reduced_destroy(vx_reduced *r) {
+    delete r;
+    return VX_OK;
 }

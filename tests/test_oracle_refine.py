@@ -292,3 +292,47 @@ def test_tangent_fallback_first_face_normal(y1, gam, kap):
     ys = np.linspace(-1, 2, 3001)
     f_plane = [abs(_plain_trilerp(re, im, np.array([0.5, yy, 0.5]))) ** 2 for yy in ys]
     assert rho <= min(f_plane) + 1e-5
+
+
+def test_seeded_refinement_closed_form_and_identity():
+    """A caller's seed replaces the face-centre estimate: the face-centre estimate itself as seed gives
+    the unseeded result bit for bit, and on a linear field (trilinear exact) the refined point from any
+    seed is the seed's projection onto the nodal line along the pseudo-vorticity a x b."""
+    rng = np.random.default_rng(31)
+    psi, cells, cdesc = _tangle_samples(seed=8, limit=200)
+    S = oracle.refine(psi, cells, cdesc)
+    seeds = np.array([x0_of_desc(int(d)) for d in cdesc])
+    T = oracle.refine(psi, cells, cdesc, seeds=seeds)
+    assert np.array_equal(S.x, T.x) and np.array_equal(S.status, T.status)
+    idx = np.arange(4) - 1.0
+    zz, yy, xx = np.meshgrid(idx, idx, idx, indexing="ij")
+    done = 0
+    for _ in range(60):
+        a, b = rng.standard_normal(3), rng.standard_normal(3)
+        p = rng.uniform(0.3, 0.7, 3)
+        X = np.stack([xx, yy, zz], -1) - p
+        scale = 2.0 ** int(rng.integers(-3, 3))
+        grid = (scale * (X @ a + 1j * (X @ b))).astype(np.complex128)
+        # an open 4x4x4 grid holding just this patch: its cell (1, 1, 1) (id 21) is the patch's centre
+        W = oracle.winding(grid.astype(np.complex64), 0)
+        if 21 not in W.cells.tolist():
+            continue
+        i = W.cells.tolist().index(21)
+        seed = rng.uniform(0.1, 0.9, 3)
+        R = oracle.refine(grid.astype(np.complex64), W.cells[i:i + 1], W.cdesc[i:i + 1], periodic=0,
+                          seeds=seed[None, :])
+        if R.status[0] & (oracle.BOUNDARY | oracle.TANGENT_FALLBACK):
+            continue
+        # the FP32 node values are the exact linear field of the FP32-rounded coefficients: refit them
+        vals = grid.astype(np.complex64).astype(np.complex128).reshape(-1)
+        A = np.c_[xx.reshape(-1), yy.reshape(-1), zz.reshape(-1), np.ones(64)]
+        cr = np.linalg.lstsq(A, vals.real, rcond=None)[0]
+        ci = np.linalg.lstsq(A, vals.imag, rcond=None)[0]
+        t = np.cross(cr[:3], ci[:3])
+        t /= np.linalg.norm(t)
+        # the nodal line: Re = Im = 0; its point closest to the seed along the plane normal to t
+        M = np.array([cr[:3], ci[:3], t])
+        expect = np.linalg.solve(M, [-cr[3], -ci[3], t @ seed])
+        assert np.abs(R.x[0] - expect).max() < 1e-6, (R.x[0], expect)
+        done += 1
+    assert done > 20
