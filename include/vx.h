@@ -381,6 +381,19 @@ vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char 
                       vx_stream s);
 
 /* ------------------------------------------------------------------------------------------
+ * Density for the error metric of the vectorised lines (Sec. 5: e = sum_i rho(x_i) / (mean rho * N)
+ * over N points x_i of the lines; rho = 0 on a true core).
+ *   vx_density       d_rho float[n] = |psi|^2 at d_points double[n][3] (grid coordinates; wrapped on
+ *                    periodic axes, extrapolated from the last cell on open ones), psi linearly
+ *                    interpolated between nodes (Sec. 5) in the refinement's FP32 arithmetic. Every
+ *                    axis needs >= 2 nodes.
+ *   vx_mean_density  *d_out (device double) = mean over all nodes of |psi|^2, accumulated in FP64.
+ * ---------------------------------------------------------------------------------------- */
+vx_status vx_density(vx_handle *h, vx_dims dims, const void *d_psi, const double *d_points, int64_t n, float *d_rho,
+                     vx_stream s);
+vx_status vx_mean_density(vx_handle *h, vx_dims dims, const void *d_psi, double *d_out, vx_stream s);
+
+/* ------------------------------------------------------------------------------------------
  * Host consumers of the lists (host memory in and out; synchronous; no device work).
  *
  * Dual graph of the vortex lines (Sec. 3.1 graph of vortex nodes, in dual form): the vertices are
@@ -441,6 +454,30 @@ vx_status vx_reduced_get(const vx_reduced *r, double *h_pos, int64_t *h_edges, i
 vx_status vx_reduced_seeds(const vx_reduced *r, const uint64_t *h_cells, const uint16_t *h_cell_desc, int64_t n,
                            uint64_t *h_seed_cell, uint16_t *h_seed_desc, float *h_seed_off);
 vx_status vx_reduced_destroy(vx_reduced *r);
+
+/* Vectorisation (Sec. 3.4) of a sample graph (positions h_pos double[n][3] in grid coordinates,
+ * undirected edges h_edges int64[nedge][2]; e.g. vx_reduced_get's output after refinement): the graph
+ * is split at its ends and branch points (connectivity other than 2) into chains -- from each such
+ * node in ascending order, along its edges in ascending neighbour order, through connectivity-2
+ * nodes to the next such node; what remains are loops, each started at its lowest node towards its
+ * lower neighbour (Type II lines, closed curves); an isolated node is a chain of one point. Each
+ * chain's samples are unwrapped along it (minimum image on periodic axes) and interpolated by a
+ * uniform Catmull-Rom spline: seg_points points per segment plus the last point (a loop closes on
+ * its first node, shifted by the loop's lattice displacement if it winds round the periodic grid);
+ * open chains repeat their end points as outer control points. Curve length = length of that
+ * polyline. Host memory; synchronous.
+ *   vx_curves_info  number of curves, points, chain nodes, and the total length
+ *   vx_curves_get   (each nullable) h_pt_start int64[ncurve+1] (curve c: points [start[c],
+ *                   start[c+1])), h_points double[npoint][3], h_length double[ncurve], h_closed
+ *                   int32[ncurve], h_node_start int64[ncurve+1], h_nodes int64[nnode] (the ordered
+ *                   sample nodes of each chain) */
+typedef struct vx_curves vx_curves;
+vx_status vx_curves_build(vx_dims dims, const double *h_pos, int64_t n, const int64_t *h_edges, int64_t nedge,
+                          int seg_points, vx_curves **out);
+vx_status vx_curves_info(const vx_curves *c, int64_t *ncurve, int64_t *npoint, int64_t *nnode, double *total_length);
+vx_status vx_curves_get(const vx_curves *c, int64_t *h_pt_start, double *h_points, double *h_length, int32_t *h_closed,
+                        int64_t *h_node_start, int64_t *h_nodes);
+vx_status vx_curves_destroy(vx_curves *c);
 
 /* ------------------------------------------------------------------------------------------
  * Kernel timing with HIP events on the launch stream (measurement support).

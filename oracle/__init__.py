@@ -350,6 +350,37 @@ def trilerp(re, im, x, lo=(-1, -1, -1), hi=(2, 2, 2)):
     return out[0] + 1j * out[1], out[2:5] + 1j * out[5:8]
 
 
+def density_at(psi: np.ndarray, points: np.ndarray, periodic: int = 7) -> np.ndarray:
+    """|psi|^2 at points (grid coordinates, rows (x, y, z)) with psi linearly interpolated between
+    nodes (Sec. 5), FP64: each point wrapped on periodic axes, in the cell that holds it (on an open
+    axis the cell of min corner 0 .. n - 2 nearest to it, extrapolating)."""
+    nz, ny, nx = psi.shape
+    dims = (nx, ny, nz)
+    out = np.empty(len(points), np.float64)
+    for k, p in enumerate(np.asarray(points, np.float64)):
+        c, u = [], []
+        for q in range(3):
+            x = p[q]
+            if (periodic >> q) & 1:
+                x = x - dims[q] * np.floor(x / dims[q])
+                f = int(np.floor(x))
+                u.append(x - f)
+                c.append(f % dims[q])
+            else:
+                f = min(max(int(np.floor(x)), 0), dims[q] - 2)
+                u.append(x - f)
+                c.append(f)
+        v = 0j
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    w = (u[0] if dx else 1 - u[0]) * (u[1] if dy else 1 - u[1]) * (u[2] if dz else 1 - u[2])
+                    node = psi[(c[2] + dz) % nz, (c[1] + dy) % ny, (c[0] + dx) % nx]
+                    v += w * complex(node)
+        out[k] = abs(v) ** 2
+    return out
+
+
 def gather_patch(psi: np.ndarray, cell: int):
     """4x4x4 patch around a cell of a periodic grid, as (re, im) arrays indexed [c][b][a]."""
     nz, ny, nx = psi.shape

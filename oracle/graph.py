@@ -206,3 +206,90 @@ def reduce_graph(dims, periodic, cells, cdesc, box_k, max_passes):
             break
     edges = sorted((u, w) for u in range(len(pos)) for w in adj[u] if u < w)
     return np.array(pos, np.float64).reshape(-1, 3), edges, members, comp, passes
+
+
+# ----------------------------------------------------------------------------------------------
+# vectorisation (Sec. 3.4): chains split at branch points and Catmull-Rom curves
+# ----------------------------------------------------------------------------------------------
+
+def chains(n, edges):
+    """Ordered node chains of a sample graph: from every node of connectivity other than 2 (ascending),
+    along each unused edge (ascending neighbour), through connectivity-2 nodes to the next such node;
+    then the remaining loops, each from its lowest node towards its lower neighbour.
+    Returns a list of (nodes, closed)."""
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    adj = [sorted(a) for a in adj]
+    used = set()
+    out = []
+    for v in range(n):
+        if len(adj[v]) == 2:
+            continue
+        if not adj[v]:
+            out.append(([v], False))
+            continue
+        for w in adj[v]:
+            if (v, w) in used:
+                continue
+            ch = [v, w]
+            used |= {(v, w), (w, v)}
+            prev, cur = v, w
+            while len(adj[cur]) == 2:
+                nxt = adj[cur][0] if adj[cur][1] == prev else adj[cur][1]
+                used |= {(cur, nxt), (nxt, cur)}
+                ch.append(nxt)
+                prev, cur = cur, nxt
+            out.append((ch, False))
+    for v in range(n):
+        if len(adj[v]) != 2 or (v, adj[v][0]) in used:
+            continue
+        ch = [v]
+        prev, cur = v, min(adj[v])
+        used |= {(v, cur), (cur, v)}
+        while cur != v:
+            ch.append(cur)
+            nxt = adj[cur][0] if adj[cur][1] == prev else adj[cur][1]
+            used |= {(cur, nxt), (nxt, cur)}
+            prev, cur = cur, nxt
+        out.append((ch, True))
+    return out
+
+
+def catmull_rom_point(a, b, c, d, t):
+    """Uniform Catmull-Rom: the cubic through b (t = 0) and c (t = 1) with tangents (c - a) / 2 and
+    (d - b) / 2."""
+    t2 = t * t
+    t3 = t2 * t
+    return [0.5 * ((2.0 * b[q]) + (c[q] - a[q]) * t + (2.0 * a[q] - 5.0 * b[q] + 4.0 * c[q] - d[q]) * t2 +
+                   (3.0 * b[q] - a[q] - 3.0 * c[q] + d[q]) * t3) for q in range(3)]
+
+
+def curve(dims, periodic, pos, nodes, closed, seg):
+    """Catmull-Rom polyline of one chain and its length."""
+    m = len(nodes)
+    P = [list(pos[nodes[0]])]
+    for i in range(1, m + 1):
+        d = _disp(dims, periodic, pos[nodes[i - 1]], pos[nodes[i % m]])
+        P.append([P[-1][q] + d[q] for q in range(3)])
+    shift = [P[m][q] - P[0][q] for q in range(3)]
+
+    def ctrl(i):
+        if not closed:
+            return P[min(max(i, 0), m - 1)]
+        turns, j = divmod(i, m)
+        return [P[j][q] + turns * shift[q] for q in range(3)]
+
+    nseg = m if closed else m - 1
+    pts = []
+    for i in range(nseg):
+        for j in range(seg):
+            pts.append(catmull_rom_point(ctrl(i - 1), ctrl(i), ctrl(i + 1), ctrl(i + 2), j / seg))
+    pts.append(list(ctrl(nseg)))
+    length = 0.0
+    for k in range(len(pts) - 1):
+        dx, dy, dz = (pts[k + 1][q] - pts[k][q] for q in range(3))
+        length += math.sqrt(dx * dx + dy * dy + dz * dz)
+    return pts, length

@@ -32,6 +32,8 @@ EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status
            "vx_gen_line_ring", "vx_winding", "vx_wind_config", "vx_refine_defaults", "vx_refine",
            "vx_refine_noalloc", "vx_node_circulation", "vx_graph_lines",
            "vx_reduce", "vx_reduced_info", "vx_reduced_get", "vx_reduced_seeds", "vx_reduced_destroy",
+           "vx_curves_build", "vx_curves_info", "vx_curves_get", "vx_curves_destroy",
+           "vx_density", "vx_mean_density",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
@@ -147,6 +149,17 @@ def lib() -> ctypes.CDLL:
         L.vx_reduced_destroy.argtypes = [P]
         for name in ("vx_reduce", "vx_reduced_info", "vx_reduced_get", "vx_reduced_seeds", "vx_reduced_destroy"):
             getattr(L, name).restype = st
+        L.vx_curves_build.argtypes = [Dims, P, ctypes.c_int64, P, ctypes.c_int64, i, ctypes.POINTER(P)]
+        L.vx_curves_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+        L.vx_curves_get.argtypes = [P, P, P, P, P, P, P]
+        L.vx_curves_destroy.argtypes = [P]
+        for name in ("vx_curves_build", "vx_curves_info", "vx_curves_get", "vx_curves_destroy"):
+            getattr(L, name).restype = st
+        L.vx_density.argtypes = [P, Dims, P, P, ctypes.c_int64, P, P]
+        L.vx_density.restype = st
+        L.vx_mean_density.argtypes = [P, Dims, P, P, P]
+        L.vx_mean_density.restype = st
         L.vx_node_circulation.argtypes = [P, Dims, P, P, P, ctypes.c_int64, P, P]
         L.vx_node_circulation.restype = st
         L.vx_refine_noalloc.argtypes = [Dims, P, P, P, P, P, ctypes.c_int64, ctypes.POINTER(RefineParams), P, P]
@@ -329,6 +342,42 @@ def vx_reduce(d: Dims, cells, cdesc, box_k: int, max_passes: int = 5):
         L.vx_reduced_destroy(r)
     return {"pos": pos, "edges": edges, "members": members, "comp": comp, "passes": npass.value,
             "seed_cell": seed_cell, "seed_desc": seed_desc, "seed_off": seed_off}
+
+
+def vx_curves(d: Dims, pos, edges, seg_points: int = 8):
+    """Catmull-Rom curves of a sample graph (host arrays): dict with pt_start, points, length, closed,
+    node_start, nodes, total_length."""
+    import numpy as np
+    pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+    edges = np.ascontiguousarray(edges, np.int64).reshape(-1, 2)
+    L = lib()
+    c = ctypes.c_void_p()
+    st = L.vx_curves_build(d, pos.ctypes.data, len(pos), edges.ctypes.data, len(edges), int(seg_points),
+                           ctypes.byref(c))
+    if st != VX_OK:
+        raise VxError(st, f"vx_curves_build: {L.vx_status_str(st).decode()}")
+    try:
+        nc, npt, nn, tot = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        L.vx_curves_info(c, ctypes.byref(nc), ctypes.byref(npt), ctypes.byref(nn), ctypes.byref(tot))
+        r = {"pt_start": np.empty(nc.value + 1, np.int64), "points": np.empty((npt.value, 3), np.float64),
+             "length": np.empty(nc.value, np.float64), "closed": np.empty(nc.value, np.int32),
+             "node_start": np.empty(nc.value + 1, np.int64), "nodes": np.empty(nn.value, np.int64)}
+        L.vx_curves_get(c, *(r[k].ctypes.data for k in ("pt_start", "points", "length", "closed", "node_start",
+                                                         "nodes")))
+        r["total_length"] = tot.value
+    finally:
+        L.vx_curves_destroy(c)
+    return r
+
+
+def vx_density(h, d: Dims, psi, points, rho, stream=None):
+    """rho (float32 [n]) = |trilinear psi|^2 at points (float64 [n, 3] device tensor)."""
+    _check(h, lib().vx_density(h, d, _ptr(psi), _ptr(points), int(points.shape[0]), _ptr(rho), _stream(stream)),
+           "vx_density")
+
+
+def vx_mean_density(h, d: Dims, psi, out, stream=None):
+    _check(h, lib().vx_mean_density(h, d, _ptr(psi), _ptr(out), _stream(stream)), "vx_mean_density")
 
 
 def vx_node_circulation(h, d: Dims, wind, count, node=None, nodes=None, stream=None):

@@ -12,7 +12,7 @@ OUT = os.path.join(HERE, "libvx.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["vx_runtime.hip", "vx_gen.hip", "vx_wind.hip", "vx_refine.hip", "vx_batch.hip", "vx_mlp.hip",
-           "vx_node.hip"]
+           "vx_node.hip", "vx_density.hip"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
@@ -27,6 +27,7 @@ PER_FILE = {
     # refinement kernels, which share their arithmetic as inline functions, round alike whatever
     # the surrounding control flow
     "vx_refine.hip": ["-ffp-contract=on"],
+    "vx_density.hip": ["-ffp-contract=on"],
 }
 
 

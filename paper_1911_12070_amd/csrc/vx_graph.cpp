@@ -424,3 +424,215 @@ extern "C" vx_status vx_reduced_destroy(vx_reduced *r) {
     delete r;
     return VX_OK;
 }
+
+// ------------------------------------------------------------------------------------------------
+// Vectorisation (Sec. 3.4): chains split at branch points, re-ordered from their starting points,
+// and uniform Catmull-Rom curves through the ordered samples.
+
+namespace vxg {
+
+struct Curves {
+    std::vector<int64_t> node_start{0};  // chain c: nodes[node_start[c] .. node_start[c+1])
+    std::vector<int64_t> nodes;
+    std::vector<int32_t> closed;
+    std::vector<int64_t> pt_start{0};    // curve c: pts[pt_start[c] .. pt_start[c+1]) (3 doubles each)
+    std::vector<double> pts;
+    std::vector<double> len;
+    double total = 0.0;
+};
+
+// Point at parameter t of the uniform Catmull-Rom segment from b to c (neighbours a and d).
+inline void catmull_rom(const double *a, const double *b, const double *c, const double *d, double t, double *o) {
+    const double t2 = t * t, t3 = t2 * t;
+    for (int q = 0; q < 3; ++q)
+        o[q] = 0.5 * ((2.0 * b[q]) + (c[q] - a[q]) * t + (2.0 * a[q] - 5.0 * b[q] + 4.0 * c[q] - d[q]) * t2 +
+                      (3.0 * b[q] - a[q] - 3.0 * c[q] + d[q]) * t3);
+}
+
+// The curve of one chain: its control points unwrapped along the chain (each one the previous plus
+// the minimum-image displacement), end points repeated for an open chain, wrapped around (shifted by
+// the loop's lattice displacement) for a closed one; `seg` points per segment, then the last point.
+inline void chain_curve(const Geom &geo, const std::vector<double> &pos, const int64_t *nodes, int64_t m, bool closed,
+                        int seg, Curves &cv) {
+    std::vector<double> P(3 * (size_t)(m + 1));
+    for (int q = 0; q < 3; ++q) P[q] = pos[3 * nodes[0] + q];
+    for (int64_t i = 1; i <= m; ++i) {
+        const int64_t prev = nodes[i - 1], cur = nodes[i % m];
+        double dd[3];
+        geo.disp(&pos[3 * prev], &pos[3 * cur], dd);
+        for (int q = 0; q < 3; ++q) P[3 * i + q] = P[3 * (i - 1) + q] + dd[q];
+    }
+    // P[m] is the closing point of a loop (node 0 after one turn)
+    const double shift[3] = {P[3 * m] - P[0], P[3 * m + 1] - P[1], P[3 * m + 2] - P[2]};
+    auto ctrl = [&](int64_t i, double *o) {  // control point i of the chain, any integer i
+        if (!closed) {
+            const int64_t j = std::min<int64_t>(std::max<int64_t>(i, 0), m - 1);
+            for (int q = 0; q < 3; ++q) o[q] = P[3 * j + q];
+            return;
+        }
+        int64_t turns = 0, j = i;
+        while (j < 0) {
+            j += m;
+            --turns;
+        }
+        while (j >= m) {
+            j -= m;
+            ++turns;
+        }
+        for (int q = 0; q < 3; ++q) o[q] = P[3 * j + q] + (double)turns * shift[q];
+    };
+    const int64_t nseg = closed ? m : m - 1;
+    double length = 0.0, last[3] = {0, 0, 0};
+    bool have = false;
+    auto emit = [&](const double *o) {
+        if (have) {
+            const double dx = o[0] - last[0], dy = o[1] - last[1], dz = o[2] - last[2];
+            length += std::sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        for (int q = 0; q < 3; ++q) {
+            cv.pts.push_back(o[q]);
+            last[q] = o[q];
+        }
+        have = true;
+    };
+    double a[3], b[3], c[3], d[3], o[3];
+    for (int64_t i = 0; i < nseg; ++i) {
+        ctrl(i - 1, a);
+        ctrl(i, b);
+        ctrl(i + 1, c);
+        ctrl(i + 2, d);
+        for (int j = 0; j < seg; ++j) {
+            catmull_rom(a, b, c, d, (double)j / (double)seg, o);
+            emit(o);
+        }
+    }
+    ctrl(nseg, o);  // the end of the last segment (a loop's closing point; a single node's only point)
+    emit(o);
+    cv.pt_start.push_back((int64_t)cv.pts.size() / 3);
+    cv.len.push_back(length);
+    cv.total += length;
+}
+
+inline void build_curves(const Geom &geo, const std::vector<double> &pos, int64_t n, const std::vector<int64_t> &start,
+                         const std::vector<int64_t> &nbr, int seg, Curves &cv) {
+    std::vector<int64_t> deg(n);
+    for (int64_t v = 0; v < n; ++v) deg[v] = start[v + 1] - start[v];
+    std::vector<char> used(nbr.size(), 0);
+    auto mark = [&](int64_t u, int64_t w) {  // mark edge u-w used in both directions
+        for (int64_t e = start[u]; e < start[u + 1]; ++e)
+            if (nbr[e] == w) used[e] = 1;
+        for (int64_t e = start[w]; e < start[w + 1]; ++e)
+            if (nbr[e] == u) used[e] = 1;
+    };
+    std::vector<int64_t> chain;
+    auto finish = [&](bool closed) {
+        cv.nodes.insert(cv.nodes.end(), chain.begin(), chain.end());
+        cv.node_start.push_back((int64_t)cv.nodes.size());
+        cv.closed.push_back(closed ? 1 : 0);
+        chain_curve(geo, pos, chain.data(), (int64_t)chain.size(), closed, seg, cv);
+    };
+    // chains between ends (connectivity other than 2), from the lowest end, edges in neighbour order
+    for (int64_t v = 0; v < n; ++v) {
+        if (deg[v] == 2) continue;
+        if (deg[v] == 0) {
+            chain.assign(1, v);
+            finish(false);
+            continue;
+        }
+        for (int64_t e = start[v]; e < start[v + 1]; ++e) {
+            if (used[e]) continue;
+            chain.assign(1, v);
+            int64_t prev = v, cur = nbr[e];
+            mark(prev, cur);
+            chain.push_back(cur);
+            while (deg[cur] == 2) {
+                const int64_t a = nbr[start[cur]], b = nbr[start[cur] + 1];
+                const int64_t nxt = a == prev ? b : a;
+                mark(cur, nxt);
+                prev = cur;
+                cur = nxt;
+                chain.push_back(cur);
+            }
+            finish(false);
+        }
+    }
+    // what is left are loops of connectivity-2 nodes: from the lowest node towards its lower neighbour
+    for (int64_t v = 0; v < n; ++v) {
+        if (deg[v] != 2 || used[start[v]]) continue;
+        chain.assign(1, v);
+        int64_t prev = v, cur = std::min(nbr[start[v]], nbr[start[v] + 1]);
+        mark(prev, cur);
+        while (cur != v) {
+            chain.push_back(cur);
+            const int64_t a = nbr[start[cur]], b = nbr[start[cur] + 1];
+            const int64_t nxt = a == prev ? b : a;
+            mark(cur, nxt);
+            prev = cur;
+            cur = nxt;
+        }
+        finish(true);
+    }
+}
+
+}  // namespace vxg
+
+struct vx_curves {
+    Curves c;
+};
+
+extern "C" vx_status vx_curves_build(vx_dims dims, const double *h_pos, int64_t n, const int64_t *h_edges,
+                                     int64_t nedge, int seg_points, vx_curves **out) {
+    if (!out) return VX_ERR_INVALID;
+    *out = nullptr;
+    if (n < 0 || nedge < 0 || (n > 0 && !h_pos) || (nedge > 0 && !h_edges) || seg_points < 1 || seg_points > 1024)
+        return VX_ERR_INVALID;
+    if (dims.nx < 1 || dims.ny < 1 || dims.nz < 1 || dims.periodic > 7u) return VX_ERR_INVALID;
+    try {
+        std::vector<std::pair<int64_t, int64_t>> pairs;
+        for (int64_t e = 0; e < nedge; ++e) {
+            const int64_t u = h_edges[2 * e], v = h_edges[2 * e + 1];
+            if (u < 0 || u >= n || v < 0 || v >= n) return VX_ERR_INVALID;
+            pairs.emplace_back(u, v);
+        }
+        PGraph g;
+        g.n = n;
+        csr_from_pairs(n, pairs, g);
+        std::vector<double> pos(h_pos, h_pos + 3 * n);
+        Geom geo{{(double)dims.nx, (double)dims.ny, (double)dims.nz},
+                 {(int)(dims.periodic & 1u), (int)((dims.periodic >> 1) & 1u), (int)((dims.periodic >> 2) & 1u)}};
+        vx_curves *cv = new vx_curves();
+        build_curves(geo, pos, n, g.start, g.nbr, seg_points, cv->c);
+        *out = cv;
+        return VX_OK;
+    } catch (const std::bad_alloc &) {
+        return VX_ERR_NOMEM;
+    }
+}
+
+extern "C" vx_status vx_curves_info(const vx_curves *cv, int64_t *ncurve, int64_t *npoint, int64_t *nnode,
+                                    double *total_length) {
+    if (!cv) return VX_ERR_INVALID;
+    if (ncurve) *ncurve = (int64_t)cv->c.len.size();
+    if (npoint) *npoint = (int64_t)cv->c.pts.size() / 3;
+    if (nnode) *nnode = (int64_t)cv->c.nodes.size();
+    if (total_length) *total_length = cv->c.total;
+    return VX_OK;
+}
+
+extern "C" vx_status vx_curves_get(const vx_curves *cv, int64_t *h_pt_start, double *h_points, double *h_length,
+                                   int32_t *h_closed, int64_t *h_node_start, int64_t *h_nodes) {
+    if (!cv) return VX_ERR_INVALID;
+    const Curves &c = cv->c;
+    if (h_pt_start) std::memcpy(h_pt_start, c.pt_start.data(), c.pt_start.size() * sizeof(int64_t));
+    if (h_points) std::memcpy(h_points, c.pts.data(), c.pts.size() * sizeof(double));
+    if (h_length) std::memcpy(h_length, c.len.data(), c.len.size() * sizeof(double));
+    if (h_closed) std::memcpy(h_closed, c.closed.data(), c.closed.size() * sizeof(int32_t));
+    if (h_node_start) std::memcpy(h_node_start, c.node_start.data(), c.node_start.size() * sizeof(int64_t));
+    if (h_nodes) std::memcpy(h_nodes, c.nodes.data(), c.nodes.size() * sizeof(int64_t));
+    return VX_OK;
+}
+
+extern "C" vx_status vx_curves_destroy(vx_curves *cv) {
+    delete cv;
+    return VX_OK;
+}

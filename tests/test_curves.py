@@ -1,0 +1,97 @@
+"""Vectorisation (Sec. 3.4): chains split at branch points, uniform Catmull-Rom curves, lengths; and
+the density at points of the error metric (Sec. 5). Oracle pins from geometry; the library's host
+implementation (vx_curves) against the oracle bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import vxinputs
+from oracle import graph as G
+
+
+def lib_curves(dims, periodic, pos, edges, seg=8):
+    from paper_1911_12070_amd import dims as mk, vx_curves
+    return vx_curves(mk(*dims, periodic), np.asarray(pos, np.float64), np.asarray(edges, np.int64).reshape(-1, 2), seg)
+
+
+def oracle_curves(dims, periodic, pos, edges, seg=8):
+    out = []
+    for nodes, closed in G.chains(len(pos), [tuple(e) for e in np.asarray(edges).reshape(-1, 2).tolist()]):
+        pts, L = G.curve(dims, periodic, [list(p) for p in np.asarray(pos, np.float64)], nodes, closed, seg)
+        out.append((nodes, closed, np.array(pts), L))
+    return out
+
+
+def assert_same(C, O):
+    assert len(C["length"]) == len(O)
+    for c, (nodes, closed, pts, L) in enumerate(O):
+        assert C["nodes"][C["node_start"][c]:C["node_start"][c + 1]].tolist() == nodes
+        assert bool(C["closed"][c]) == closed
+        assert np.array_equal(C["points"][C["pt_start"][c]:C["pt_start"][c + 1]], pts)
+        assert C["length"][c] == L
+
+
+def test_spline_interpolates_and_circle_length():
+    R, m = 6.0, 24
+    th = 2 * np.pi * np.arange(m) / m
+    pos = np.c_[20 + R * np.cos(th), 20 + R * np.sin(th), np.full(m, 10.0)]
+    edges = [(i, (i + 1) % m) for i in range(m)]
+    O = oracle_curves((40, 40, 20), 0, pos, edges)
+    assert len(O) == 1 and O[0][1]  # one closed chain
+    nodes, closed, pts, L = O[0]
+    assert np.allclose(pts[::8][:m], pos[nodes], atol=1e-12)  # passes through every sample
+    assert abs(L - 2 * np.pi * R) / (2 * np.pi * R) < 2e-3
+    # collinear equally spaced samples: the curve is the segment, traversed once
+    line = np.c_[np.arange(7) * 1.5 + 1, np.full(7, 3.0), np.full(7, 2.0)]
+    O = oracle_curves((40, 40, 20), 0, line, [(i, i + 1) for i in range(6)])
+    assert len(O) == 1 and not O[0][1] and abs(O[0][3] - 9.0) < 1e-12
+
+
+def test_chains_split_at_branch_points():
+    # figure eight: two loops through node 0
+    pos = np.array([[5, 5, 5], [6, 5, 5], [6, 6, 5], [5, 6, 5], [4, 5, 5], [4, 4, 5], [5, 4, 5]], float)
+    eight = [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (4, 5), (5, 6), (6, 0)]
+    ch = G.chains(7, eight)
+    assert len(ch) == 2 and all(not c for _, c in ch) and all(n[0] == 0 and n[-1] == 0 for n, _ in ch)
+    # theta: two branch nodes joined by three paths; plus an isolated node
+    theta = [(0, 1), (1, 2), (0, 3), (3, 2), (0, 4), (4, 2)]
+    ch = G.chains(6, theta)
+    assert sorted((n[0], n[-1], len(n)) for n, _ in ch) == [(0, 2, 3)] * 3 + [(5, 5, 1)]
+    # a straight line winding once round a periodic axis closes with the lattice shift
+    zpos = np.c_[np.full(8, 3.5), np.full(8, 4.5), np.arange(8) * 4.0 + 0.5]
+    O = oracle_curves((9, 9, 32), 4, zpos, [(i, (i + 1) % 8) for i in range(8)])
+    assert len(O) == 1 and O[0][1] and abs(O[0][3] - 32.0) < 1e-12
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_library_curves_equal_oracle(k):
+    from paper_1911_12070_amd import dims, vx_reduce
+    cases = [(vxinputs.eval_tangle(vxinputs.make_tangle((64, 64, 64), 256, (3, 7), 3), (0, 0, 0, 48, 40, 36)), 7),
+             (vxinputs.eval_tangle(vxinputs.make_tangle((64, 64, 64), 256, (3, 7), 4), (0, 0, 0, 48, 40, 36)), 0),
+             (vxinputs.eval_line_ring(vxinputs.line_ring_32()), 7)]
+    for psi, per in cases:
+        nz, ny, nx = psi.shape
+        W = oracle.winding(psi, per)
+        R = vx_reduce(dims(nx, ny, nz, per), W.cells, W.cdesc, k, 5)
+        assert_same(lib_curves((nx, ny, nz), per, R["pos"], R["edges"]),
+                    oracle_curves((nx, ny, nz), per, R["pos"], R["edges"]))
+    pos = np.array([[5, 5, 5], [6, 5, 5], [6, 6, 5], [5, 6, 5], [4, 5, 5], [4, 4, 5], [5, 4, 5], [9, 9, 9]], float)
+    eight = [(0, 1), (1, 2), (2, 3), (3, 0), (0, 4), (4, 5), (5, 6), (6, 0)]
+    assert_same(lib_curves((12, 12, 12), 7, pos, eight), oracle_curves((12, 12, 12), 7, pos, eight))
+
+
+def test_oracle_density_closed_forms():
+    rng = np.random.default_rng(5)
+    a, b = rng.standard_normal(3), rng.standard_normal(3)
+    p = np.array([3.3, 2.7, 4.1])
+    zz, yy, xx = np.meshgrid(np.arange(8), np.arange(7), np.arange(9), indexing="ij")
+    X = np.stack([xx, yy, zz], -1) - p
+    psi = (X @ a + 1j * (X @ b)).astype(np.complex128)
+    pts = rng.uniform(0, 6, (50, 3))
+    rho = oracle.density_at(psi, pts, periodic=0)
+    d = pts - p
+    assert np.allclose(rho, (d @ a) ** 2 + (d @ b) ** 2, rtol=1e-12, atol=1e-12)  # trilinear is exact
+    nodes = np.c_[xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)][:40].astype(float)
+    assert np.allclose(oracle.density_at(psi, nodes, 7), np.abs(psi.reshape(-1)[:40]) ** 2, rtol=1e-14)
