@@ -217,6 +217,68 @@ def bench_node_circulation(ex, wind, steps: int):
             "nodes_per_s": nodes / (ms * 1e-3)}
 
 
+def bench_vectorisation(ex, psi, out, nf: int, nc: int, box_k: int = 4):
+    """The consumers of the benchmark's lists: dual graph and line classes, box-mean samples with graph
+    reduction (host C++), their refinement from the box-mean seeds (GPU), Catmull-Rom curves (host),
+    and the density error metric e at the box means, the refined samples and the curve points (GPU
+    density kernels). Wall times of the host steps, HIP-event times of the GPU ones."""
+    import numpy as np
+    import torch
+
+    from paper_1911_12070_amd import (KIND_REFINE, dims, samples_to_numpy, vx_curves, vx_density, vx_graph_lines,
+                                      vx_mean_density, vx_profile_enable, vx_profile_read, vx_reduce, vx_refine)
+    print("[bench] vectorisation consumers", file=sys.stderr, flush=True)
+    nz, ny, nx = psi.shape
+    d = dims(nx, ny, nz, 7)
+    cells = out["cells"][:nc].cpu().numpy().view(np.uint64)
+    cdesc = out["cdesc"][:nc].cpu().numpy().view(np.uint16)
+    t0 = time.perf_counter()
+    comp, deg, types, st = vx_graph_lines(d, cells, cdesc)
+    t1 = time.perf_counter()
+    R = vx_reduce(d, cells, cdesc, box_k, 5)
+    t2 = time.perf_counter()
+    m = len(R["seed_cell"])
+    dev = psi.device
+    sc = torch.from_numpy(R["seed_cell"].view(np.int64)).to(dev)
+    sd = torch.from_numpy(R["seed_desc"].view(np.int16)).to(dev)
+    so = torch.from_numpy(R["seed_off"]).to(dev)
+    cnt = torch.tensor([m], dtype=torch.int64, device=dev)
+    smp = torch.empty((m, 8), dtype=torch.int32, device=dev)
+    vx_refine(ex.h, d, psi, sc, sd, cnt, smp, seed=so, cap=m)
+    torch.cuda.synchronize()
+    vx_profile_enable(ex.h, True)
+    for _ in range(5):
+        vx_refine(ex.h, d, psi, sc, sd, cnt, smp, seed=so, cap=m)
+    ref_ms, k = vx_profile_read(ex.h, KIND_REFINE)
+    vx_profile_enable(ex.h, False)
+    s = samples_to_numpy(smp, m)
+    c = R["seed_cell"].astype(np.int64)
+    xstar = np.stack([c % nx, (c // nx) % ny, c // (nx * ny)], 1).astype(np.float64) + s["off"].astype(np.float64)
+    t3 = time.perf_counter()
+    C = vx_curves(d, xstar, R["edges"], 8)
+    t4 = time.perf_counter()
+    rbar = torch.zeros(1, dtype=torch.float64, device=dev)
+    vx_mean_density(ex.h, d, psi, rbar)
+    rbar = float(rbar.cpu())
+    e = {}
+    for tag, pts in (("box_means", R["pos"]), ("refined_samples", xstar), ("curve_points", C["points"])):
+        p = torch.from_numpy(np.ascontiguousarray(pts)).to(dev)
+        rho = torch.empty(len(pts), dtype=torch.float32, device=dev)
+        vx_density(ex.h, d, psi, p, rho)
+        e[tag] = float(rho.double().sum().cpu()) / (rbar * len(pts))
+    ok = (s["status"] & (8 | 16)) == 0
+    return {
+        "box_k": box_k,
+        "graph": {"lines": st["ncomp"], "by_type": st["ntype"], "branch_cells": st["nbranch"], "host_s": t1 - t0},
+        "reduction": {"cells": nc, "samples": m, "passes": R["passes"], "host_s": t2 - t1},
+        "seeded_refinement": {"kernel_ms": ref_ms / max(k, 1), "converged_fraction": float(ok.mean())},
+        "curves": {"count": len(C["length"]), "closed": int(C["closed"].sum()), "points": len(C["points"]),
+                   "total_length_cells": C["total_length"], "host_s": t4 - t3},
+        "error_metric_e": e,
+        "mean_density": rbar,
+    }
+
+
 def calib_copy():
     """Kernels of known traffic: their FETCH_SIZE / WRITE_SIZE readings calibrate the counters
     (fill: writes 1 GiB; sum: reads 1 GiB)."""
@@ -447,6 +509,7 @@ def main():
         },
     }
     res["node_circulation"] = bench_node_circulation(ex, out["wind"], args.steps)
+    res["vectorisation"] = bench_vectorisation(ex, psi, out, nf, nc)
     del out, samples
     torch.cuda.empty_cache()
     res["pipelined"] = bench_pipeline(ex, psi, args.steps, args.warmup, cap, wl, N)

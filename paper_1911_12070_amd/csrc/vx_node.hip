@@ -158,6 +158,216 @@ __global__ __launch_bounds__(64) void node_circ_k(NodeArgs A) {
     flush();
 }
 
+// Wide rows: rows whose length is a multiple of 16 nodes and 16-byte aligned fields. A wavefront owns
+// WROWS consecutive rows of a 1024-node segment (16 nodes per lane, one 16-byte word per row) plus the
+// row below them, and marches along z. Per row and plane it forms B (the biased x and z fields,
+// bits 0-1 and 4-5 of each byte, in one mask-add-mask) and Y (the biased y field); the ring sums then
+// reuse pair sums across rows and planes:
+//   T = B(row) + B(row - 1):  Sx = T + T(previous plane) (low nibbles), Sz = T + T(x - 1) (high nibbles)
+//   U = Y + Y(previous plane): Sy = U + U(x - 1).
+// The neighbour x - 1 of a lane's first node is the previous lane's last byte; lane 0 reads the
+// segment's neighbour bytes itself and keeps their y fields for the next plane. The three sums of a
+// node (each 0..8) index the table as Sx + 9 Sy + 81 Sz, formed two nodes at a time in 16-bit halves.
+// Vortex nodes are counted per lane, placed by a wavefront prefix sum into LDS and flushed as in
+// node_circ_k. The results are node_circ_k's bit for bit.
+constexpr int WROWS = 4;  // output rows per wavefront
+
+__device__ __forceinline__ uint32_t bxz(uint32_t w) {  // biased x and z fields (w + 1 per 2-bit field)
+    return ((w & 0x33333333u) + 0x11111111u) & 0x33333333u;
+}
+__device__ __forceinline__ uint32_t byf(uint32_t w) {  // biased y field
+    return (((w >> 2) & 0x03030303u) + 0x01010101u) & 0x03030303u;
+}
+// per-node values of nodes x - 1: byte i of word t -> byte i + 1; `in` holds the value of the node
+// before the lane's first in its top byte
+__device__ __forceinline__ void xshift4(const uint32_t v[4], uint32_t in, uint32_t o[4]) {
+    o[0] = __builtin_amdgcn_alignbyte(v[0], in, 3);
+    o[1] = __builtin_amdgcn_alignbyte(v[1], v[0], 3);
+    o[2] = __builtin_amdgcn_alignbyte(v[2], v[1], 3);
+    o[3] = __builtin_amdgcn_alignbyte(v[3], v[2], 3);
+}
+// the previous lane's v (all lanes active; the empty asm keeps the move outside any branch)
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+    uint32_t p = (uint32_t)__shfl_up((int)v, 1);
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
+__global__ __launch_bounds__(64) void node_circ_wide_k(NodeArgs A) {
+    __shared__ uint8_t s_lut[LUT];
+    __shared__ uint64_t s_buf[NBUF];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < LUT; e += 64) s_lut[e] = lut_entry(e);
+    __syncthreads();
+
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
+    const int xw = blockIdx.x * 1024;  // first node of the wavefront's segment
+    const int i0 = xw + 16 * lane;     // first of this lane's 16 nodes
+    const bool active = i0 < nx;       // nx is a multiple of 16: a lane is wholly inside or outside
+    const int j0 = blockIdx.y * WROWS;
+    const int z0 = blockIdx.z * NODE_ZC, z1 = min(z0 + NODE_ZC, nz);
+    const int im = xw > 0 ? xw - 1 : (A.px ? nx - 1 : -1);  // node x - 1 of the segment's first node
+
+    // grid row of wavefront row q (q = 0: the row below j0; q >= 1: j0 + q - 1); -1 if absent
+    int rows[WROWS + 1];
+#pragma unroll
+    for (int q = 0; q <= WROWS; ++q) {
+        const int j = j0 + q - 1;
+        rows[q] = j < 0 ? (A.py ? ny - 1 : -1) : (j < ny ? j : -1);
+    }
+    auto rowbase = [&](int j, int k) -> uint64_t {
+        return (uint64_t)nx * ((uint64_t)j + (uint64_t)ny * (uint64_t)k);
+    };
+    auto load_row = [&](int j, int k, uint32_t w[4]) {
+        w[0] = w[1] = w[2] = w[3] = 0u;
+        if (j < 0 || k < 0 || !active) return;
+        const uint4 v = *(const uint4 *)(A.wind + rowbase(j, k) + i0);
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    };
+    auto edge_byte = [&](int j, int k) -> uint32_t {  // node im of row j (lane 0's neighbour)
+        return (lane == 0 && im >= 0 && j >= 0 && k >= 0) ? (uint32_t)A.wind[rowbase(j, k) + (uint64_t)im] : 0u;
+    };
+
+    int cnt = 0;
+    auto flush = [&]() {
+        if (cnt == 0) return;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        unsigned long long base = 0;
+        if (lane == 0) {
+            base = atomicAdd(reinterpret_cast<unsigned long long *>(A.count), (unsigned long long)cnt);
+            if ((int64_t)base + cnt > A.cap) atomicOr(A.flag, (unsigned long long)VX_OVERFLOW_WIND);
+        }
+        base = ((unsigned long long)(uint32_t)__shfl((int)(base >> 32), 0) << 32) | (uint32_t)__shfl((int)base, 0);
+        for (int q = lane; q < cnt; q += 64) {
+            const int64_t idx = (int64_t)base + q;
+            if (idx < A.cap) A.list[idx] = s_buf[q];
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __builtin_amdgcn_wave_barrier();
+        cnt = 0;
+    };
+
+    // state carried from the previous plane, per output row: T, Y (and lane 0's neighbour y field)
+    uint32_t Tp[WROWS][4], Yp[WROWS][4], yim[WROWS];
+    {
+        const int kp = z0 > 0 ? z0 - 1 : (A.pz ? nz - 1 : -1);
+        uint32_t w[4], Bb[4];
+        load_row(rows[0], kp, w);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Bb[t] = bxz(w[t]);
+#pragma unroll
+        for (int q = 1; q <= WROWS; ++q) {
+            load_row(rows[q], kp, w);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t b = bxz(w[t]);
+                Tp[q - 1][t] = b + Bb[t];
+                Bb[t] = b;
+                Yp[q - 1][t] = byf(w[t]);
+            }
+            yim[q - 1] = byf(edge_byte(rows[q], kp));
+        }
+    }
+    for (int k = z0; k < z1; ++k) {
+        uint32_t w[4], Bb[4];
+        load_row(rows[0], k, w);
+        uint32_t eb = edge_byte(rows[0], k);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Bb[t] = bxz(w[t]);
+        uint32_t Bbe = bxz(eb);  // lane 0: B of the neighbour node of the row below
+        int nv = 0;              // vortex nodes of this lane in this plane
+        uint32_t out[WROWS][4];
+#pragma unroll
+        for (int q = 1; q <= WROWS; ++q) {
+            load_row(rows[q], k, w);
+            const uint32_t e = edge_byte(rows[q], k);
+            uint32_t T[4], U[4], Tx[4], Ux[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t b = bxz(w[t]), y = byf(w[t]);
+                T[t] = b + Bb[t];
+                Bb[t] = b;
+                U[t] = y + Yp[q - 1][t];
+                Yp[q - 1][t] = y;
+            }
+            // values of the node before the lane's first: the previous lane's last, or lane 0's own
+            const uint32_t be = bxz(e), ye = byf(e);
+            uint32_t tin = from_prev_lane(T[3]), uin = from_prev_lane(U[3]);
+            if (lane == 0) {
+                tin = (be + Bbe) << 24;
+                uin = (ye + yim[q - 1]) << 24;
+            }
+            Bbe = be;
+            yim[q - 1] = ye;
+            xshift4(T, tin, Tx);
+            xshift4(U, uin, Ux);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t Sx = (T[t] + Tp[q - 1][t]) & 0x0F0F0F0Fu;
+                const uint32_t Sz = ((T[t] + Tx[t]) >> 4) & 0x0F0F0F0Fu;
+                const uint32_t Sy = U[t] + Ux[t];
+                Tp[q - 1][t] = T[t];
+                const uint32_t ie = (Sx & 0x00FF00FFu) + 9u * (Sy & 0x00FF00FFu) + 81u * (Sz & 0x00FF00FFu);
+                const uint32_t io =
+                    ((Sx >> 8) & 0x00FF00FFu) + 9u * ((Sy >> 8) & 0x00FF00FFu) + 81u * ((Sz >> 8) & 0x00FF00FFu);
+                const uint32_t o = (uint32_t)s_lut[ie & 0xffffu] | ((uint32_t)s_lut[io & 0xffffu] << 8) |
+                                   ((uint32_t)s_lut[ie >> 16] << 16) | ((uint32_t)s_lut[io >> 16] << 24);
+                out[q - 1][t] = (active && rows[q] >= 0) ? o : 0u;
+                nv += __popc(out[q - 1][t] & 0x40404040u);
+            }
+        }
+        if (A.node) {
+#pragma unroll
+            for (int q = 1; q <= WROWS; ++q)
+                if (active && rows[q] >= 0)
+                    *(uint4 *)(A.node + rowbase(rows[q], k) + i0) =
+                        make_uint4(out[q - 1][0], out[q - 1][1], out[q - 1][2], out[q - 1][3]);
+        }
+        // vortex nodes: per-lane counts, a wavefront prefix sum, entries into LDS
+        if (__ballot(nv != 0) != 0) {
+            int incl = nv;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(incl, off);
+                if (lane >= off) incl += v;
+            }
+            const int total = __shfl(incl, 63);
+            if (cnt + total > NBUF) flush();
+            int64_t pos = cnt + incl - nv;  // LDS slot of this lane's first entry
+            unsigned long long gbase = 0;
+            if (total > NBUF) {  // more than the buffer holds: every lane reserves its own slots
+                if (nv) {
+                    gbase = atomicAdd(reinterpret_cast<unsigned long long *>(A.count), (unsigned long long)nv);
+                    if ((int64_t)gbase + nv > A.cap) atomicOr(A.flag, (unsigned long long)VX_OVERFLOW_WIND);
+                }
+            }
+#pragma unroll
+            for (int q = 1; q <= WROWS; ++q)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    uint32_t m = out[q - 1][t] & 0x40404040u;
+                    while (m) {
+                        const int bb = __builtin_ctz(m) >> 3;
+                        m &= m - 1;
+                        const uint64_t id = rowbase(rows[q], k) + (uint64_t)(i0 + 4 * t + bb);
+                        if (total > NBUF) {
+                            if ((int64_t)gbase < A.cap) A.list[gbase] = id;
+                            ++gbase;
+                        } else {
+                            s_buf[pos++] = id;
+                        }
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();
+            if (total <= NBUF) cnt += total;
+        }
+    }
+    flush();
+}
+
 __global__ void zero_count_k(int64_t *c) {
     if (threadIdx.x == 0) *c = 0;
 }
@@ -192,9 +402,15 @@ extern "C" vx_status vx_node_circulation(vx_handle *h, vx_dims dims, const uint8
     A.aligned = (dims.nx % 4 == 0) && ((uintptr_t)d_wind & 3u) == 0 && ((uintptr_t)d_node & 3u) == 0;
     hipStream_t hs = (hipStream_t)s;
     hipLaunchKernelGGL(zero_count_k, dim3(1), dim3(64), 0, hs, d_count);
-    const dim3 grid((unsigned)((dims.nx + 255) / 256), (unsigned)dims.ny, (unsigned)((dims.nz + NODE_ZC - 1) / NODE_ZC));
+    // whole 16-node words per lane when rows allow it (node_circ_wide_k), else 4 nodes per lane
+    const bool wide = dims.nx % 16 == 0 && ((uintptr_t)d_wind & 15u) == 0 && ((uintptr_t)d_node & 15u) == 0;
+    const unsigned gz = (unsigned)((dims.nz + NODE_ZC - 1) / NODE_ZC);
     vx_timer tm(h, hs, VX_KIND_NODE);
-    hipLaunchKernelGGL(node_circ_k, grid, dim3(64), 0, hs, A);
+    if (wide)
+        hipLaunchKernelGGL(node_circ_wide_k, dim3((unsigned)((dims.nx + 1023) / 1024), (unsigned)((dims.ny + WROWS - 1) / WROWS), gz),
+                           dim3(64), 0, hs, A);
+    else
+        hipLaunchKernelGGL(node_circ_k, dim3((unsigned)((dims.nx + 255) / 256), (unsigned)dims.ny, gz), dim3(64), 0, hs, A);
     tm.stop();
     return vx_hip_check(h, hipGetLastError(), "node_circ_k launch");
 }

@@ -1,7 +1,8 @@
 """Node-centred circulation on the GPU (vx_node_circulation) against the oracle: every node byte and
 the sorted vortex-node list bit for bit, on the GPU's own packed field (itself bit-exact with the
 oracle's), for ragged and tile-boundary shapes, every periodic mask, degenerate small-integer
-fields, tangles up to 512^3 and the 1024^3 benchmark field (in z-slabs)."""
+fields (dense in vortex nodes), tangles and the 1024^3 benchmark field (in z-slabs). Rows whose
+length is a multiple of 16 take the wide kernel, the others the general one."""
 import numpy as np
 import pytest
 
@@ -45,7 +46,10 @@ def w_from_packed(packed):
 
 CASES = [((7, 5, 4), 7, "int"), ((13, 9, 6), 0, "int"), ((256, 3, 3), 5, "int"), ((260, 6, 5), 7, "int"),
          ((31, 17, 70), 3, "int"), ((96, 80, 64), 7, "tangle"), ((100, 66, 70), 6, "tangle"),
-         ((257, 40, 33), 1, "tangle"), ((64, 64, 130), 4, "tangle"), ((2, 2, 2), 7, "int")]
+         ((257, 40, 33), 1, "tangle"), ((64, 64, 130), 4, "tangle"), ((2, 2, 2), 7, "int"),
+         # whole 16-node words per lane (the wide kernel): two row segments, open and periodic axes,
+         # rows not a multiple of the rows per wavefront
+         ((1040, 6, 5), 5, "int"), ((112, 9, 70), 0, "tangle"), ((16, 3, 2), 7, "int"), ((2048, 5, 3), 2, "int")]
 
 
 @pytest.mark.parametrize("shape,periodic,kind", CASES)
