@@ -212,7 +212,10 @@ def bench_node_circulation(ex, wind, steps: int):
     alg = 2 * nodes + 8 * nv + 8
     del node, lst
     torch.cuda.empty_cache()
-    return {"kernel": "node_circ_k", "kernel_ms": ms, "vortex_nodes": nv, "algorithmic_bytes_per_launch": alg,
+    # the library takes the wide-row kernel when rows are whole 16-node words (torch buffers are
+    # 256-byte aligned)
+    kname = "node_circ_wide_k" if nx % 16 == 0 else "node_circ_k"
+    return {"kernel": kname, "kernel_ms": ms, "vortex_nodes": nv, "algorithmic_bytes_per_launch": alg,
             "achieved_GBs": alg / (ms * 1e-3) / 1e9, "frac_of_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "nodes_per_s": nodes / (ms * 1e-3)}
 
