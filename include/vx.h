@@ -365,8 +365,9 @@ vx_status vx_batch_launch_eager(vx_batch *b, vx_stream s);
 /* Planes per z-chunk used for frame f (after autotuning, the tuned value). */
 vx_status vx_batch_zchunk(const vx_batch *b, int frame, int *zchunk);
 /* Autotune the z-chunk depth of every distinct frame shape for this batch, by coordinate descent
- * over {8, 16, 32, 64, 128} (values above nz dropped), timing the batched winding launch with HIP
- * events on s (median of 3 after one warm-up); synchronises s. cache_path (nullable) is a JSON
+ * over {8, 16, 32, 64, 128} (values above nz dropped) in two sweeps over the shapes, timing the
+ * batched winding launch with HIP events on s (median of 7 after one warm-up); synchronises s.
+ * cache_path (nullable) is a JSON
  * file of earlier results, one object per line: {"kind": "batch", "dims": [nx, ny, nz],
  * "periodic": p, "zchunk": z}; entries found there are used without timing, new results are
  * appended. The graph is captured again with the chosen depths. */
@@ -374,8 +375,9 @@ vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_stream s);
 vx_status vx_batch_destroy(vx_batch *b);
 
 /* Autotune the z-chunk depth of vx_winding for one grid shape on the caller's field d_psi
- * (same candidates and timing as above, with internal scratch outputs allocated for the
- * duration of the call; synchronises s); the handle then uses it for that shape.
+ * (same candidates as above, one pass, timing the winding launch with HIP events on s, median of
+ * 3 after one warm-up, with internal scratch outputs allocated for the duration of the call;
+ * synchronises s); the handle then uses it for that shape.
  * cache_path as above with "kind": "grid". *zchunk (nullable) receives the choice. */
 vx_status vx_autotune(vx_handle *h, vx_dims dims, const void *d_psi, const char *cache_path, int *zchunk,
                       vx_stream s);
