@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void density_k(DensArgs A, const double *__res
     float tr, ti;
     V3 tgr, tgi;
     trilinear(cf, u, tr, ti, tgr, tgi);
-    rho[i] = tr * tr + ti * ti;
+    rho[i] = vxr::rho2(tr, ti);
 }
 
 __global__ void zero_d_k(double *p) {

@@ -207,7 +207,7 @@ __device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const f
         tri_coeffs(C, cf);
     }
     trilinear(cf, uo, vr, vi, gr, gi);
-    rho = vr * vr + vi * vi;
+    rho = vxr::rho2(vr, vi);
     if (max_step > 0.f && rho != 0.f) {
         if (!newton_dir(vr, vi, plane_jac(gr, gi, e1, e2), n1, n2, den)) return false;
         const float q1 = n1 * den, q2 = n2 * den;

@@ -28,6 +28,11 @@ using namespace vxr;
 
 constexpr int REF_THREADS = 256;  // four wavefronts per workgroup
 constexpr int REF_CHUNK = 64;     // samples a wavefront claims at a time
+constexpr int REF_SPEC = 2;       // trial points a lane may evaluate per pass (sequential rule)
+// resident refine_k workgroups per CU at most: with two trial points per pass each wavefront has
+// more independent work, and four wavefronts per SIMD beat five (0.65 against 0.67 ms on the 1024^3
+// tangle's list, 0.275 against 0.30 ms on the 512^3 one); three were slower (0.70 ms)
+constexpr int REF_WG_PER_CU = 4;
 
 struct RefArgs {
     const float2 *psi;
@@ -116,11 +121,8 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     bool more = true;  // unclaimed chunks may remain
     auto claim = [&](int64_t ci) {
         if constexpr (BATCH) {
-            if (ci >= s_cstart[nframes]) {
-                more = false;
-                next = end = 0;
-                return;
-            }
+            // (no early return: it kept the bounds in memory)
+            const bool have = ci < s_cstart[nframes];
             int lo = 0, hi = nframes;  // last frame whose first chunk is <= ci
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -128,8 +130,10 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
                 else hi = mid;
             }
             cf = __builtin_amdgcn_readfirstlane(lo);
-            next = uni64((ci - s_cstart[cf]) * REF_CHUNK);
-            end = uni64(min(s_items[cf], next + REF_CHUNK));
+            const int64_t nx = uni64((ci - s_cstart[cf]) * REF_CHUNK);
+            next = have ? nx : 0;
+            end = have ? uni64(min(s_items[cf], nx + REF_CHUNK)) : 0;
+            more = more && have;
         } else {
             next = min(n_items, ci * chunk);
             end = min(n_items, next + chunk);
@@ -285,9 +289,51 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         const bool init = phase == PH_INIT;
         const bool tri = phase == PH_TRIAL;
         const bool descent = mode == MODE_DESCENT;
-        const float ft = tr * tr + ti * ti;
-        const bool acc = tri && (descent ? (ft <= f - P.armijo * alpha * gn) : (ft < f));
+        const float fa = rho2(tr, ti);
+        bool acc = tri && (descent ? (fa <= f - P.armijo * alpha * gn) : (fa < f));
+        // a rejected trial point is followed by the one at half its step, and so on: up to
+        // REF_SPEC - 1 of these are evaluated in the same pass, from the cached polynomial, while each
+        // lies in the cell just evaluated (inside the patch, within the halving limit and, for Newton,
+        // not the current point; other cases are left to the sequential rule of the next pass). The
+        // points, tests and halvings are those of the sequential rule, so results do not change; a step
+        // that needs one or two halvings costs one pass instead of two or three.
+        if (tri && !acc) {
+            bool go = true;
+#pragma unroll
+            for (int q = 1; q < REF_SPEC; ++q) {
+                const float ah = 0.5f * alpha;
+                const float sy1 = y1 + ah * p1, sy2 = y2 + ah * p2;
+                const V3 xs = plane_point(x0, e1, e2, sy1, sy2);
+                int cs[3];
+                float us[3];
+                const int code = locate(xs, box, cs, us);
+                go = go && hv + 1 < P.max_halvings && in_patch(xs, box) &&
+                     !(mode == MODE_NEWTON && sy1 == y1 && sy2 == y2) && code == ccode;
+                if (go) {
+                    float2 v[8];
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) v[d] = s_corner[d][tid];
+                    float br, bi;
+                    V3 bgr, bgi;
+                    trilinear(v, us, br, bi, bgr, bgi);
+                    const float fb = rho2(br, bi);
+                    alpha = ah;  // the previous point's rejection
+                    ++hv;
+                    if (descent ? (fb <= f - P.armijo * alpha * gn) : (fb < f)) {
+                        tr = br;
+                        ti = bi;
+                        tgr = bgr;
+                        tgi = bgi;
+                        ty1 = sy1;
+                        ty2 = sy2;
+                        acc = true;
+                        go = false;
+                    }
+                }
+            }
+        }
         const bool take = init || acc;
+        const float ft = rho2(tr, ti);  // of the point taken (the first one, or a later one of the pass)
         y1 = take ? ty1 : y1;
         y2 = take ? ty2 : y2;
         vr = take ? tr : vr;
@@ -490,7 +536,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
         plane_basis(tgr, tgi, desc, e1, e2, status);
         float y1 = 0.f, y2 = 0.f, vr = tr, vi = ti;
         V3 gr = tgr, gim = tgi;
-        float f = tr * tr + ti * ti;
+        float f = rho2(tr, ti);
         float s_prev = 0.5f * P.step0, gn = 0.f;
         float alpha = 0.f, p1 = 0.f, p2 = 0.f;  // current step: length at halving hv, direction
         int mode = MODE_DESCENT, dit = 0, nit = 0, hv = 0;
@@ -537,7 +583,7 @@ __global__ __launch_bounds__(REF_THREADS) void refine_spec_k(RefArgs A, int64_t 
             // a lane that does not evaluate keeps stale values, which are never taken: only an
             // accepting lane's are broadcast
             if (inside && !stuck) eval(xt, tr, ti, tgr, tgi);
-            const float ft = tr * tr + ti * ti;
+            const float ft = rho2(tr, ti);
             const bool descent = mode == MODE_DESCENT;
             const bool acc = inside && !stuck && (descent ? (ft <= f - P.armijo * a * gn) : (ft < f));
             const uint32_t res = (uint32_t)(__ballot(stuck || acc) >> gl) & ((1u << SPEC_G) - 1u);
@@ -610,11 +656,19 @@ int occupancy(K kernel) {
     return nb > 0 ? nb : 1;
 }
 
-// one resident round of wavefronts (they claim chunks dynamically); fewer for short lists; -1 on error
+// resident workgroups per CU of refine_k: what fits, at most REF_WG_PER_CU; -1 on error
+int long_per_cu() {
+    const int r = occupancy(refine_k<false>);
+    return r < 0 ? -1 : std::min(r, REF_WG_PER_CU);
+}
+
+// one resident round of wavefronts (they claim chunks dynamically, at most REF_WG_PER_CU workgroups
+// per CU); fewer for short lists; -1 on error
 template <typename K>
 int64_t ref_blocks(vx_handle *h, K kernel, int &per_cu, int64_t cap) {
     if (per_cu <= 0) {
         per_cu = occupancy(kernel);
+        if (per_cu > REF_WG_PER_CU) per_cu = REF_WG_PER_CU;
         if (per_cu < 0) {
             vx_fail(h, VX_ERR_DEVICE, "refinement kernel occupancy query failed");
             return -1;
@@ -682,7 +736,7 @@ RefArgs make_args(const vx_dims &d, const void *psi, const uint64_t *cells, cons
 vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, const uint64_t *cells,
                            const uint16_t *desc, const float *seed, const int64_t *count, int64_t cap,
                            const vx_refine_params &p, vx_sample *out, hipStream_t s, const int64_t *out_index) {
-    if (h->ref_blocks_per_cu <= 0) h->ref_blocks_per_cu = occupancy(refine_k<false>);
+    if (h->ref_blocks_per_cu <= 0) h->ref_blocks_per_cu = long_per_cu();
     if (h->refs_blocks_per_cu <= 0) h->refs_blocks_per_cu = occupancy(refine_spec_k);
     if (h->ref_blocks_per_cu < 0 || h->refs_blocks_per_cu < 0)
         return vx_fail(h, VX_ERR_DEVICE, "refinement kernel occupancy query failed");
@@ -739,7 +793,7 @@ vx_status noalloc_setup(int dev, NoallocDev &nd) {
     int num_cu = 0;
     if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || num_cu <= 0)
         return VX_ERR_DEVICE;
-    const int r = occupancy(refine_k<false>), sp = occupancy(refine_spec_k);
+    const int r = long_per_cu(), sp = occupancy(refine_spec_k);
     if (r < 0 || sp < 0) return VX_ERR_DEVICE;
     nd.scratch = (unsigned long long *)ptr;
     nd.cfg = RefCfg{num_cu, r, sp, 8};

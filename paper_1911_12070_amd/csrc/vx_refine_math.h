@@ -237,6 +237,11 @@ __device__ __forceinline__ void plane_basis(const V3 &tgr, const V3 &tgi, uint32
     e2 = crs(t, e1);
 }
 
+// |psi|^2 from (Re psi, Im psi), one fused multiply-add in a fixed order: every kernel that compares
+// densities forms them through this function, so that equal values compare equal whatever the
+// compiler contracts elsewhere
+__device__ __forceinline__ float rho2(float re, float im) { return fmaf(re, re, im * im); }
+
 // the point x0 + y1 e1 + y2 e2
 __device__ __forceinline__ V3 plane_point(const V3 &x0, const V3 &e1, const V3 &e2, float y1, float y2) {
     VX_CONTRACT_ON
