@@ -176,9 +176,11 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
     uint32_t xstep = cvalid;
     if (!A.px && ncol > 0 && xl0 + ncol == nx) xstep &= ~(1u << (ncol - 1));
     const int xh = x0 + TXO < nx ? x0 + TXO : (A.px ? (x0 + TXO) % nx : nx - 1);
-    // interior tiles use 16-byte loads of whole rows; others (ragged last column tile, odd nx) load
-    // per node
-    const bool fast = A.psi_a16 && (x0 + TXO <= nx) && ((nx & 1) == 0);
+    // even rows use 16-byte loads of whole tile rows (in a ragged last column tile, the pieces past
+    // the grid's end are the wrapped ones on a periodic axis, any valid one otherwise, as those
+    // columns are never used); odd nx loads per node
+    const bool xin = x0 + TXO <= nx;
+    const bool fast = A.psi_a16 && ((nx & 1) == 0) && (xin || nx >= TXO);
     const bool yin = y0 + 16 <= ny;
 
     const float2 *psi = A.psi;
@@ -195,21 +197,29 @@ __device__ __forceinline__ void wind_tile(const WindArgs &A, int tile) {
         const float2 *pl = psi + (uint64_t)plane_of(k) * plane_nodes;
         if (fast) {
             const int cc = lane >> 4, xx = lane & 15;
-            // row j: lane L lands at slot L; it fetches the piece whose rotated slot is L
-            auto row_load = [&](int j, const float2 *row) {
-                const int q = 16 * cc + ((xx - j - 4 * cc) & 15);
-                __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(row + 2 * q),
-                                                 (void __attribute__((address_space(3))) *)(s_plane + j * 1024),
-                                                 16, 0, 0);
-            };
-            if (yin) {  // rows y0 .. y0+15 of the grid: one pointer stepped by a row (uniform branch)
+            auto lds_row = [&](int j) { return (void __attribute__((address_space(3))) *)(s_plane + j * 1024); };
+            if (xin && yin) {  // rows y0 .. y0+15 of the grid: one pointer stepped by a row (uniform branch)
+                // row j: lane L lands at slot L; it fetches the piece whose rotated slot is L
                 const float2 *row = pl + (uint64_t)y0 * nx + x0;
 #pragma unroll
-                for (int j = 0; j < 16; ++j, row += nx) row_load(j, row);
-            } else {  // the tile reaches past the last grid row: wrapped or clamped rows (a loop, so
-                      // that no row pointer stays live across the march)
+                for (int j = 0; j < 16; ++j, row += nx) {
+                    const int q = 16 * cc + ((xx - j - 4 * cc) & 15);
+                    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(row + 2 * q),
+                                                     lds_row(j), 16, 0, 0);
+                }
+            } else {  // the tile reaches past the last grid row or column: wrapped or clamped rows, and
+                      // pieces past the last column wrapped (periodic; nx >= 128, so once) or clamped
+                      // (their columns are never used); a loop, so that no row pointer stays live across
+                      // the march, and pinned lane coordinates, so that no per-row column does
+                const int ccr = (int)pin((uint32_t)cc), xxr = (int)pin((uint32_t)xx);
 #pragma unroll 1
-                for (int j = 0; j < 16; ++j) row_load(j, pl + (uint64_t)row_of(j) * nx + x0);
+                for (int j = 0; j < 16; ++j) {
+                    int col = x0 + 2 * (16 * ccr + ((xxr - j - 4 * ccr) & 15));
+                    if (col >= nx) col = A.px ? col - nx : nx - 2;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void __attribute__((address_space(1))) *)(pl + (uint64_t)row_of(j) * nx + col), lds_row(j),
+                        16, 0, 0);
+                }
             }
         } else {
             const float2 *rowp = pl + (uint64_t)yl * nx;
