@@ -312,6 +312,7 @@ def bench_series(args):
     print("[bench] autotuning z-chunk depths", file=sys.stderr, flush=True)
     batch.autotune(None, stream)
     tuned = {t.dims[0]: batch.zchunk(f) for f, t in enumerate(tangles)}
+    refine_wg = batch.refine_wg()
     for _ in range(args.warmup):
         batch.launch(stream)
     torch.cuda.synchronize()
@@ -362,6 +363,7 @@ def bench_series(args):
             "cells": cells,
             "frames_per_size": {str(k): series.sizes.count(k) for k in sorted(set(series.sizes))},
             "zchunk_per_size": {str(k): v for k, v in sorted(tuned.items())},
+            "refine_workgroups_per_cu": refine_wg,
             "pierced_faces": nf_all,
             "pierced_cells": nc_all,
         },

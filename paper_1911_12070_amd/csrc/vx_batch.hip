@@ -9,8 +9,10 @@
 //
 // The autotuner picks the planes marched per wavefront (z-chunk depth) of the winding kernel. Deeper
 // chunks re-read fewer halo planes; shallower ones make more tiles, which a lone small grid needs to
-// fill the GPU but a batch does not. Candidates are timed with HIP events; results can be kept in a
-// JSON-lines cache file.
+// fill the GPU but a batch does not. For a batch it then picks the refinement's resident workgroups
+// per CU (more hide latency; fewer leave each wavefront's lanes more cache and issue slots), timing
+// the refinement of the batch's own lists. Candidates are timed with HIP events; z-chunk results can
+// be kept in a JSON-lines cache file.
 #include <algorithm>
 #include <cstring>
 #include <fstream>
@@ -25,6 +27,7 @@ struct vx_batch {
     std::vector<vx_frame> frames;
     vx_refine_params p{};
     std::vector<int> zc;  // planes per z-chunk of each frame
+    int ref_wg = 0;       // resident refinement workgroups per CU (0: the library's default)
     vx_wind_args *d_wargs = nullptr;
     int *d_tile_start = nullptr;
     vx_ref_frame *d_rframes = nullptr;
@@ -183,7 +186,8 @@ vx_status enqueue(vx_batch *b, hipStream_t s, bool timed = false) {
     }
     if (b->n_ref == 0) return VX_OK;
     vx_timer tm(b->h, s, timed ? VX_KIND_REFINE : -1);
-    const vx_status st = vx_refine_batch_enqueue(b->h, b->d_rframes, b->n_ref, b->total_cap, b->p, b->d_counter, s);
+    const vx_status st =
+        vx_refine_batch_enqueue(b->h, b->d_rframes, b->n_ref, b->total_cap, b->p, b->d_counter, b->ref_wg, s);
     tm.stop();
     return st;
 }
@@ -295,6 +299,12 @@ extern "C" vx_status vx_batch_zchunk(const vx_batch *b, int frame, int *zchunk) 
     return VX_OK;
 }
 
+extern "C" vx_status vx_batch_refine_wg(const vx_batch *b, int *wg_per_cu) {
+    if (!b || !wg_per_cu) return VX_ERR_INVALID;
+    *wg_per_cu = b->ref_wg;
+    return VX_OK;
+}
+
 extern "C" vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_stream s) {
     if (!b) return VX_ERR_INVALID;
     vx_handle *h = b->h;
@@ -346,8 +356,26 @@ extern "C" vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_s
                 if (key_of(b->frames[f].dims) == k) zc = b->zc[f];
             append_cache(cache_path, "batch", k, zc, best_ms[k]);
         }
-    h->profile = prof;
     if (st == VX_OK) st = upload(b);
+    // resident refinement workgroups per CU, on the lists of one winding with the chosen depths
+    if (st == VX_OK && b->n_ref > 0) {
+        st = enqueue_wind(b, hs);
+        const int top = vx_refine_batch_max_wg(h);
+        int best_wg = 0;
+        double best = 1e30;
+        for (int wg = 2; st == VX_OK && wg <= top; ++wg) {
+            double ms = 0.0;
+            st = time_median(h, hs, 7, [&] {
+                return vx_refine_batch_enqueue(h, b->d_rframes, b->n_ref, b->total_cap, b->p, b->d_counter, wg, hs);
+            }, &ms);
+            if (st == VX_OK && ms < best) {
+                best = ms;
+                best_wg = wg;
+            }
+        }
+        if (st == VX_OK) b->ref_wg = best_wg;
+    }
+    h->profile = prof;
     if (st == VX_OK) st = capture(b);
     return st;
 }

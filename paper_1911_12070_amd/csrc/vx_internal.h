@@ -125,5 +125,9 @@ int vx_wind_zc_for(vx_handle *h, const vx_dims &d);
 vx_status vx_wind_batch_enqueue(vx_handle *h, const vx_wind_args *d_frames, const int *d_tile_start, int nframes,
                                 int64_t total_tiles, hipStream_t s);
 // one launch refining the listed cells of several grids (table in device memory)
+// wg_per_cu > 0: resident refinement workgroups per CU to launch (capped by what fits); 0: the default
 vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
-                                  const vx_refine_params &p, unsigned long long *d_counter, hipStream_t s);
+                                  const vx_refine_params &p, unsigned long long *d_counter, int wg_per_cu,
+                                  hipStream_t s);
+// resident workgroups per CU that the batch refinement kernel can have at most (-1 on error)
+int vx_refine_batch_max_wg(vx_handle *h);

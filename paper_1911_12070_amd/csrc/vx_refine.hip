@@ -748,16 +748,27 @@ vx_status vx_refine_launch(vx_handle *h, const vx_dims &d, const void *psi, cons
     return vx_hip_check(h, e, "refine launch");
 }
 
+int vx_refine_batch_max_wg(vx_handle *h) {
+    (void)h;
+    return occupancy(refine_k<true>);
+}
+
 vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,
-                                  const vx_refine_params &p, unsigned long long *d_counter, hipStream_t s) {
+                                  const vx_refine_params &p, unsigned long long *d_counter, int wg_per_cu,
+                                  hipStream_t s) {
     if (nframes < 1 || nframes > VX_BATCH_MAX_FRAMES)
         return vx_fail(h, VX_ERR_INVALID, "refine batch: %d frames", nframes);
     RefArgs A{};
     A.chunks = d_counter;
     A.flag = vx_overflow_flag(h);
     A.p = p;
-    const int64_t blocks = ref_blocks(h, refine_k<true>, h->refb_blocks_per_cu, total_cap);
+    int64_t blocks = ref_blocks(h, refine_k<true>, h->refb_blocks_per_cu, total_cap);
     if (blocks < 0) return VX_ERR_DEVICE;
+    if (wg_per_cu > 0) {  // the batch's own choice, within what fits
+        const int64_t resident = (int64_t)std::min(wg_per_cu, occupancy(refine_k<true>)) * (h->num_cu > 0 ? h->num_cu : 256);
+        const int64_t need = (total_cap + 4 * REF_CHUNK - 1) / (4 * REF_CHUNK);
+        blocks = std::max<int64_t>(1, std::min(need, resident));
+    }
     hipLaunchKernelGGL(zero_u64_k, dim3(1), dim3(1), 0, s, d_counter);
     hipLaunchKernelGGL(refine_k<true>, dim3((unsigned)blocks), dim3(REF_THREADS), 0, s, A, d_frames, nframes,
                        h->ref_refill, (int64_t)-1);

@@ -154,6 +154,11 @@ class Batch:
         from . import vx_batch_autotune
         vx_batch_autotune(self.ex.h, self.b, cache_path, stream)
 
+    def refine_wg(self) -> int:
+        """Resident refinement workgroups per CU of the batch (0 until autotuned: the default)."""
+        from . import vx_batch_refine_wg
+        return vx_batch_refine_wg(self.ex.h, self.b)
+
     def zchunk(self, frame: int) -> int:
         from . import vx_batch_zchunk
         return vx_batch_zchunk(self.ex.h, self.b, frame)

@@ -117,9 +117,11 @@ def test_batch_autotune_and_cache(ex, tmp_path):
     batch.launch(graph=False)
     ref = results(batch)
     cache = str(tmp_path / "tune.jsonl")
+    assert batch.refine_wg() == 0  # the default until tuned
     batch.autotune(cache)
     chosen = [batch.zchunk(f) for f in range(len(SHAPES))]
-    log(f"tuned z-chunks {chosen}")
+    log(f"tuned z-chunks {chosen}, refinement workgroups per CU {batch.refine_wg()}")
+    assert 2 <= batch.refine_wg() <= 8
     for z, (_, _, nz, _) in zip(chosen, SHAPES):
         assert z in CANDIDATES
     lines = open(cache).read().strip().splitlines()
@@ -128,7 +130,7 @@ def test_batch_autotune_and_cache(ex, tmp_path):
     assert_same(results(batch), ref)
     batch.close()
     again = make_batch(ex, psis)
-    again.autotune(cache)  # every shape is in the cache: nothing is timed or appended
+    again.autotune(cache)  # every shape is in the cache: no depth is timed, nothing is appended
     assert [again.zchunk(f) for f in range(len(SHAPES))] == chosen
     assert open(cache).read().strip().splitlines() == lines
     again.launch()
