@@ -42,6 +42,7 @@ static_assert(NPARAM == VX_MLP_NPARAMS, "parameter count");
 
 constexpr int TM = 64;           // rows per tile
 constexpr int NT = 256;          // threads per workgroup
+constexpr int POLISH_WG_PER_CU = 5;  // polish workgroups per CU (what fits at its 87 VGPRs)
 constexpr int XP = NIN + 8;      // LDS row pitch (values) of the input tile
 constexpr int HP = NH + 8;       // LDS row pitch of a hidden tile
 constexpr int GT = 1024;         // table intervals on [-8, 8]
@@ -75,6 +76,7 @@ __device__ __forceinline__ float tab(const float2 *t, float x) {
 struct Geo {
     const float2 *psi;
     int nx, ny, nz, px, py, pz;
+    double rnx, rnxy;  // 1 / nx and 1 / (nx ny), for the cell-id split
 };
 
 __device__ __forceinline__ int wrapc(int q, int n, int per) {
@@ -84,19 +86,11 @@ __device__ __forceinline__ int wrapc(int q, int n, int per) {
 
 // cell id -> node coordinates (cells of any grid that fits in memory, < 2^53)
 __device__ __forceinline__ void cell_xyz(uint64_t cell, const Geo &g, int &i, int &j, int &k) {
-    const uint64_t nxy = (uint64_t)g.nx * (uint64_t)g.ny;
-    uint64_t q = (uint64_t)((double)cell / (double)nxy);
-    int64_t r = (int64_t)(cell - q * nxy);
-    if (r < 0) {
-        --q;
-        r += (int64_t)nxy;
-    } else if (r >= (int64_t)nxy) {
-        ++q;
-        r -= (int64_t)nxy;
-    }
-    k = (int)q;
-    j = (int)(r / g.nx);
-    i = (int)(r - (int64_t)j * g.nx);
+    // quotients by multiplication with the FP64 reciprocals, corrected by one (exact below 2^53)
+    uint64_t rxy, ri;
+    k = (int)vxr::divmod53(cell, (uint64_t)g.nx * (uint64_t)g.ny, g.rnxy, rxy);
+    j = (int)vxr::divmod53(rxy, (uint64_t)g.nx, g.rnx, ri);
+    i = (int)ri;
 }
 
 // the patch lies inside the grid (always on periodic axes)
@@ -142,11 +136,11 @@ __device__ __forceinline__ void gather_features(const Geo &g, int i, int j, int 
 // patch, or -- when max_step > 0 -- a Newton step from the polished point that would be longer than
 // max_step cells (that step estimates the polished point's distance from the zero of psi in the
 // plane, so a confident but wrong prediction goes to the plain method instead of being reported).
-// The corners of the cell itself come from ctr, 64 contiguous bytes written by the network kernel,
-// the others from the field; those of x0's cell and of xs's cell are requested together: the
+// The corners of the cell itself come in ctr (64 contiguous bytes written by the network kernel,
+// loaded by the caller together with its other inputs), the others from the field; those of x0's cell and of xs's cell are requested together: the
 // projected point and the Newton point mostly lie in one of the two, so that the evaluations usually
 // wait for one round of loads.
-__device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const float4 *ctr, const vxr::V3 &x0,
+__device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const float4 ctr[4], const vxr::V3 &x0,
                        const vxr::V3 &xs, float max_step, vxr::V3 &out, float &rho) {
     using namespace vxr;
     constexpr int CENTRE = 21;  // locate()'s code of the cell itself: (0+1) + 4 (0+1) + 16 (0+1)
@@ -861,55 +855,65 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
                                                vx_sample *out, uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
                                                int64_t *fb_count) {
     const int64_t n = min(*count, cap);
-    if ((int64_t)blockIdx.x * NT >= n) return;  // uniform per workgroup
-    const int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x;
-    bool queue = false;
-    uint64_t cell = 0;
-    uint32_t d = 0;
-    if (s < n) {
-        cell = cells[s];
-        d = desc[s];
-        uint32_t st0 = 0;
-        const vxr::V3 x0 = vxr::first_estimate(d, st0);
-        const int np = __popc((d | (d >> 1)) & 0x555u);  // pierced faces: nonzero 2-bit fields
-        const float4 o = net_out[s];
-        bool mine = np == 2 && o.w >= thr && cell < (uint64_t)g.nx * g.ny * g.nz;
-        int i = 0, j = 0, k = 0;
-        if (mine) {
-            cell_xyz(cell, g, i, j, k);
-            mine = interior(g, i, j, k);
-        }
-        if (mine) {
-            const vxr::V3 xs = vxr::v3(x0.x + o.x, x0.y + o.y, x0.z + o.z);
-            vxr::V3 x;
-            float rho = 0.f;
-            mine = polish(g, i, j, k, d, centre + 4 * s, x0, xs, max_step, x, rho);
+    // grid-stride over the listed cells: the grid is sized for the capacity only up to what the chip
+    // holds at once, so that a short list does not pay for thousands of workgroups that find nothing
+    // to do (each would wait for the count before returning)
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t s0 = (int64_t)blockIdx.x * NT; s0 < n; s0 += stride) {  // uniform per workgroup
+        const int64_t s = s0 + threadIdx.x;
+        bool queue = false;
+        uint64_t cell = 0;
+        uint32_t d = 0;
+        if (s < n) {
+            cell = cells[s];
+            d = desc[s];
+            // requested with the other inputs (one round of loads), whether the cell is polished or not
+            float4 ctr[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ctr[q] = centre[4 * s + q];
+            uint32_t st0 = 0;
+            const vxr::V3 x0 = vxr::first_estimate(d, st0);
+            const int np = __popc((d | (d >> 1)) & 0x555u);  // pierced faces: nonzero 2-bit fields
+            const float4 o = net_out[s];
+            bool mine = np == 2 && o.w >= thr && cell < (uint64_t)g.nx * g.ny * g.nz;
+            int i = 0, j = 0, k = 0;
             if (mine) {
-                vx_sample r{};
-                r.cell = cell;
-                r.off[0] = x.x;
-                r.off[1] = x.y;
-                r.off[2] = x.z;
-                r.rho = rho;
-                r.iters = 1;
-                r.status = (uint16_t)VX_SAMPLE_SURROGATE;
-                out[s] = r;
+                cell_xyz(cell, g, i, j, k);
+                mine = interior(g, i, j, k);
             }
+            if (mine) {
+                const vxr::V3 xs = vxr::v3(x0.x + o.x, x0.y + o.y, x0.z + o.z);
+                vxr::V3 x;
+                float rho = 0.f;
+                mine = polish(g, i, j, k, d, ctr, x0, xs, max_step, x, rho);
+                if (mine) {
+                    vx_sample r{};
+                    r.cell = cell;
+                    r.off[0] = x.x;
+                    r.off[1] = x.y;
+                    r.off[2] = x.z;
+                    r.rho = rho;
+                    r.iters = 1;
+                    r.status = (uint16_t)VX_SAMPLE_SURROGATE;
+                    out[s] = r;
+                }
+            }
+            queue = !mine;
         }
-        queue = !mine;
-    }
-    const uint64_t qm = __ballot(queue);
-    if (qm) {
-        const int lead = __builtin_ctzll(qm);
-        unsigned long long base = 0;
-        if ((int)(threadIdx.x & 63) == lead) base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
-        base = ((unsigned long long)(uint32_t)__shfl((int)(base >> 32), lead) << 32) | (uint32_t)__shfl((int)base, lead);
-        if (queue) {
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-            const int64_t k = (int64_t)base + rank;
-            fb_cell[k] = cell;
-            fb_desc[k] = (uint16_t)d;
-            fb_index[k] = s;
+        const uint64_t qm = __ballot(queue);
+        if (qm) {
+            const int lead = __builtin_ctzll(qm);
+            unsigned long long base = 0;
+            if ((int)(threadIdx.x & 63) == lead)
+                base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
+            base = ((unsigned long long)(uint32_t)__shfl((int)(base >> 32), lead) << 32) | (uint32_t)__shfl((int)base, lead);
+            if (queue) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+                const int64_t k = (int64_t)base + rank;
+                fb_cell[k] = cell;
+                fb_desc[k] = (uint16_t)d;
+                fb_index[k] = s;
+            }
         }
     }
 }
@@ -969,6 +973,8 @@ Geo geo_of(const vx_dims &d, const void *psi) {
     g.px = (int)(d.periodic & 1u);
     g.py = (int)((d.periodic >> 1) & 1u);
     g.pz = (int)((d.periodic >> 2) & 1u);
+    g.rnx = 1.0 / (double)d.nx;
+    g.rnxy = 1.0 / ((double)d.nx * (double)d.ny);
     return g;
 }
 
@@ -1254,7 +1260,8 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
                        d_count, cap, m->net_out, m->centre, m->fb_count, vx_overflow_flag(h));
     tm.stop();
     vx_timer tp(h, hs, VX_KIND_POLISH);
-    hipLaunchKernelGGL(polish_k, dim3((unsigned)((cap + NT - 1) / NT)), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
+    const int64_t pgrid = std::max<int64_t>(1, std::min<int64_t>((cap + NT - 1) / NT, (int64_t)POLISH_WG_PER_CU * num_cu));
+    hipLaunchKernelGGL(polish_k, dim3((unsigned)pgrid), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,
                        d_cell_desc, d_count, cap, (const float4 *)m->net_out, (const float4 *)m->centre, conf_threshold,
                        max_step, d_out, m->fb_cell,
                        m->fb_desc, m->fb_index, m->fb_count);
