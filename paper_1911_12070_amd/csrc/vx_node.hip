@@ -50,6 +50,15 @@ __device__ uint8_t lut_entry(int e) {
     return (uint8_t)(mag | (v < 0 ? 4 : 0) | (best << 3) | 0x40);
 }
 
+// The same byte for the wide kernel's index Sx | Sz << 4 | Sy << 8 (index values with a sum above 8
+// never occur; their entries are 0)
+constexpr int LUTW = 9 << 8;
+__device__ uint8_t lutw_entry(int e) {
+    const int sx = e & 15, sz = (e >> 4) & 15, sy = e >> 8;
+    if (sx > 8 || sz > 8 || sy > 8) return 0;
+    return lut_entry(sx + 9 * sy + 81 * sz);
+}
+
 // biased windings w + 1 of field a (bits 2a+1:2a of each byte) of four packed bytes
 __device__ __forceinline__ uint32_t biased(uint32_t w, int a) {
     return (((w >> (2 * a)) & 0x03030303u) + 0x01010101u) & 0x03030303u;
@@ -167,7 +176,9 @@ __global__ __launch_bounds__(64) void node_circ_k(NodeArgs A) {
 //   U = Y + Y(previous plane): Sy = U + U(x - 1).
 // The neighbour x - 1 of a lane's first node is the previous lane's last byte; lane 0 reads the
 // segment's neighbour bytes itself and keeps their y fields for the next plane. The three sums of a
-// node (each 0..8) index the table as Sx + 9 Sy + 81 Sz, formed two nodes at a time in 16-bit halves.
+// node (each 0..8) index the table as Sx | Sz << 4 | Sy << 8: one bit-field insert keeps Sx's low
+// nibbles and Sz's high ones (no sum carries out of its nibble), and one byte permute per pair of
+// nodes places the y sums above them in 16-bit halves.
 // Vortex nodes are counted per lane, placed by a wavefront prefix sum into LDS and flushed as in
 // node_circ_k. The results are node_circ_k's bit for bit.
 constexpr int WROWS = 4;  // output rows per wavefront
@@ -194,10 +205,10 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
 }
 
 __global__ __launch_bounds__(64) void node_circ_wide_k(NodeArgs A) {
-    __shared__ uint8_t s_lut[LUT];
+    __shared__ uint8_t s_lut[LUTW];
     __shared__ uint64_t s_buf[NBUF];
     const int lane = threadIdx.x;
-    for (int e = lane; e < LUT; e += 64) s_lut[e] = lut_entry(e);
+    for (int e = lane; e < LUTW; e += 64) s_lut[e] = lutw_entry(e);
     __syncthreads();
 
     const int nx = A.nx, ny = A.ny, nz = A.nz;
@@ -306,13 +317,12 @@ __global__ __launch_bounds__(64) void node_circ_wide_k(NodeArgs A) {
             xshift4(U, uin, Ux);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const uint32_t Sx = (T[t] + Tp[q - 1][t]) & 0x0F0F0F0Fu;
-                const uint32_t Sz = ((T[t] + Tx[t]) >> 4) & 0x0F0F0F0Fu;
+                // per byte: Sx in the low nibble, Sz in the high one; Sy beside
+                const uint32_t XZ = ((T[t] + Tp[q - 1][t]) & 0x0F0F0F0Fu) | ((T[t] + Tx[t]) & 0xF0F0F0F0u);
                 const uint32_t Sy = U[t] + Ux[t];
                 Tp[q - 1][t] = T[t];
-                const uint32_t ie = (Sx & 0x00FF00FFu) + 9u * (Sy & 0x00FF00FFu) + 81u * (Sz & 0x00FF00FFu);
-                const uint32_t io =
-                    ((Sx >> 8) & 0x00FF00FFu) + 9u * ((Sy >> 8) & 0x00FF00FFu) + 81u * ((Sz >> 8) & 0x00FF00FFu);
+                const uint32_t ie = __builtin_amdgcn_perm(Sy, XZ, 0x06020400u);  // nodes 0, 2
+                const uint32_t io = __builtin_amdgcn_perm(Sy, XZ, 0x07030501u);  // nodes 1, 3
                 const uint32_t o = (uint32_t)s_lut[ie & 0xffffu] | ((uint32_t)s_lut[io & 0xffffu] << 8) |
                                    ((uint32_t)s_lut[ie >> 16] << 16) | ((uint32_t)s_lut[io >> 16] << 24);
                 out[q - 1][t] = (active && rows[q] >= 0) ? o : 0u;
