@@ -7,8 +7,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (dims as make_dims, vx_create, vx_destroy, vx_gen_line_ring, vx_gen_tangle, vx_refine,
-               vx_refine_defaults, vx_winding, vx_wind_config)
+from . import (VX_ERR_CAPACITY, VxError, dims as make_dims, vx_create, vx_destroy, vx_gen_line_ring, vx_gen_tangle,
+               vx_refine, vx_refine_defaults, vx_winding, vx_wind_config)
 
 SAMPLE_DTYPE = np.dtype([("cell", "<u8"), ("off", "<f4", (3,)), ("rho", "<f4"), ("iters", "<u2"),
                          ("status", "<u2"), ("reserved", "<u4")])
@@ -116,6 +116,44 @@ class Extractor:
                   wout["counts"][1:], samples, params or vx_refine_defaults(), seed, stream,
                   cap=min(cap, samples.shape[0]))
         return samples
+
+    def vectorize(self, psi, periodic: int = 7, box_k: int = 4, max_passes: int = 5, seg_points: int = 8,
+                  wout=None, params=None):
+        """The paper's pipeline from a field to vector lines, in one call (synchronous): winding and
+        compaction on the GPU; the dual graph of the pierced cells and its line classes, box-mean
+        samples with graph reduction (host, in the library); refinement of the reduced samples from
+        their box means on the GPU; Catmull-Rom curves through the refined samples (host). Returns a
+        dict: graph (per-cell component and connectivity, class per component, counts), samples
+        (absolute positions [m, 3], the refinement records, the sample graph's edges, members and
+        components) and curves (as vx_curves returns them)."""
+        from . import vx_curves, vx_graph_lines, vx_reduce
+        torch = self.torch
+        nz, ny, nx = psi.shape
+        d = make_dims(nx, ny, nz, periodic)
+        wout = self.winding(psi, periodic, wout)
+        nf, nc = (int(v) for v in wout["counts"].cpu())
+        if nf > wout["faces"].numel() or nc > wout["cells"].numel():
+            raise VxError(VX_ERR_CAPACITY, f"vectorize: {nf} faces / {nc} cells exceed the list capacity")
+        cells = wout["cells"][:nc].cpu().numpy().view(np.uint64)
+        cdesc = wout["cdesc"][:nc].cpu().numpy().view(np.uint16)
+        comp, degree, ctype, stats = vx_graph_lines(d, cells, cdesc)
+        R = vx_reduce(d, cells, cdesc, box_k, max_passes)
+        m = len(R["seed_cell"])
+        dev = psi.device
+        smp = self.alloc_samples(max(m, 1))
+        if m:
+            vx_refine(self.h, d, psi, torch.from_numpy(R["seed_cell"].view(np.int64)).to(dev),
+                      torch.from_numpy(R["seed_desc"].view(np.int16)).to(dev),
+                      torch.tensor([m], dtype=torch.int64, device=dev), smp, params or vx_refine_defaults(),
+                      torch.from_numpy(R["seed_off"]).to(dev), None, cap=m)
+        s = samples_to_numpy(smp, m)
+        c = R["seed_cell"].astype(np.int64)
+        pos = np.stack([c % nx, (c // nx) % ny, c // (nx * ny)], 1).astype(np.float64) + s["off"].astype(np.float64)
+        curves = vx_curves(d, pos, R["edges"], seg_points)
+        return {"graph": {"comp": comp, "degree": degree, "comp_type": ctype, "stats": stats},
+                "samples": {"pos": pos, "records": s, "edges": R["edges"], "members": R["members"],
+                            "comp": R["comp"], "passes": R["passes"]},
+                "curves": curves}
 
 
 class Batch:

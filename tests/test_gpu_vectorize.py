@@ -174,3 +174,44 @@ def test_vectorize_tangle_1024():
         assert nchk > 200 and worst <= TOL
     finally:
         ex.close()
+
+
+@pytest.mark.parametrize("name", ["line_ring_32", "tangle_96_open"])
+def test_extractor_vectorize_equals_the_steps(name):
+    """Extractor.vectorize (one call from the field to curves) gives exactly what its steps give when
+    called one by one: graph, reduced samples, their refinement and the curves."""
+    import torch
+    from paper_1911_12070_amd import Extractor, dims, vx_curves, vx_graph_lines, vx_reduce
+    ex = Extractor(0)
+    try:
+        if name == "line_ring_32":
+            psi, per = ex.gen_line_ring(vxinputs.line_ring_32()), 7
+        else:
+            t = vxinputs.make_tangle((128, 128, 128), 256, (3, 7), 77)
+            psi = torch.from_numpy(vxinputs.eval_tangle(t, (0, 0, 0, 96, 80, 72))).cuda()
+            per = 0
+        nz, ny, nx = psi.shape
+        d = dims(nx, ny, nz, per)
+        V = ex.vectorize(psi, per, box_k=4, max_passes=5, seg_points=8)
+        out = ex.alloc_winding(psi.shape, face_cap=1 << 20, cell_cap=1 << 20, wind=False)
+        ex.winding(psi, per, out)
+        torch.cuda.synchronize()
+        _, _, cells, cdesc = gpu_lists(out)
+        comp, deg, types, st = vx_graph_lines(d, cells, cdesc)
+        # the list order differs between two windings (compaction order): compare what does not
+        # depend on it
+        assert V["graph"]["stats"] == st
+        assert np.array_equal(np.bincount(V["graph"]["comp_type"], minlength=4), np.bincount(types, minlength=4))
+        assert np.array_equal(np.sort(V["graph"]["degree"]), np.sort(deg))
+        # the reduction sorts the cells itself: same samples whatever the list order
+        R = vx_reduce(d, cells, cdesc, 4, 5)
+        assert np.array_equal(V["samples"]["edges"], R["edges"]) and V["samples"]["passes"] == R["passes"]
+        s, xstar = refine_seeds(ex, psi, per, R)
+        assert np.array_equal(V["samples"]["pos"], xstar)
+        assert V["samples"]["records"].tobytes() == s.tobytes()
+        C = vx_curves(d, xstar, R["edges"], 8)
+        for k in ("pt_start", "points", "length", "closed", "node_start", "nodes"):
+            assert np.array_equal(V["curves"][k], C[k]), k
+        log(f"{name}: vectorize = steps ({len(cells)} cells, {len(xstar)} samples, {len(C['length'])} curves)")
+    finally:
+        ex.close()
