@@ -542,4 +542,5 @@ def vx_profile_read(h, kind: int):
     return ms.value, n.value
 
 
-from .pipeline import Batch, Extractor, FramePipeline, upload_tangle, samples_to_numpy  # noqa: E402,F401
+from .pipeline import (Batch, Extractor, FramePipeline, length_histogram, lines_by_length,  # noqa: E402,F401
+                       samples_to_numpy, upload_tangle)

@@ -156,6 +156,25 @@ class Extractor:
                 "curves": curves}
 
 
+def lines_by_length(curves, lo: float, hi: float, scale: float = 1.0) -> np.ndarray:
+    """Indices of the curves whose length, times scale (e.g. domain size / cells per axis, for lengths
+    in units of the domain), lies in [lo, hi): the selection of the paper's multi-scale view
+    (Sec. 4.1.2), on the lengths vx_curves measures."""
+    L = np.asarray(curves["length"], np.float64) * scale
+    return np.nonzero((L >= lo) & (L < hi))[0]
+
+
+def length_histogram(curves, edges, scale: float = 1.0):
+    """Number of curves and their total length, times scale, per length bin [edges[i], edges[i+1])."""
+    L = np.asarray(curves["length"], np.float64) * scale
+    e = np.asarray(edges, np.float64)
+    which = np.searchsorted(e, L, side="right") - 1
+    inside = (which >= 0) & (which < len(e) - 1)
+    count = np.bincount(which[inside], minlength=len(e) - 1)
+    total = np.bincount(which[inside], weights=L[inside], minlength=len(e) - 1)
+    return count, total
+
+
 class Batch:
     """A vx_batch over frames (psi tensors of uneven shapes) with torch-allocated outputs.
 

@@ -95,3 +95,29 @@ def test_oracle_density_closed_forms():
     assert np.allclose(rho, (d @ a) ** 2 + (d @ b) ** 2, rtol=1e-12, atol=1e-12)  # trilinear is exact
     nodes = np.c_[xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)][:40].astype(float)
     assert np.allclose(oracle.density_at(psi, nodes, 7), np.abs(psi.reshape(-1)[:40]) ** 2, rtol=1e-14)
+
+
+def test_length_selection_and_histogram():
+    """The multi-scale view's selection by length (Sec. 4.1.2) on lengths the library measured: a
+    circle of radius 3 (length ~ 2 pi 3) and two straight segments of 1 and 4 cells."""
+    from paper_1911_12070_amd import length_histogram, lines_by_length
+    n = 24
+    ang = 2 * math.pi * np.arange(n) / n
+    circle = np.stack([10 + 3 * np.cos(ang), 10 + 3 * np.sin(ang), np.full(n, 5.0)], 1)
+    seg1 = np.array([[2.0, 2.0, 2.0], [3.0, 2.0, 2.0]])
+    seg4 = np.array([[2.0, 8.0, 2.0], [4.0, 8.0, 2.0], [6.0, 8.0, 2.0]])
+    pos = np.concatenate([circle, seg1, seg4])
+    edges = [(i, (i + 1) % n) for i in range(n)] + [(n, n + 1), (n + 2, n + 3), (n + 3, n + 4)]
+    C = lib_curves((32, 32, 32), 7, pos, edges)
+    L = C["length"]
+    assert len(L) == 3
+    short, long_ = lines_by_length(C, 0.0, 2.0), lines_by_length(C, 2.0, 100.0)
+    assert sorted(L[short].round(6).tolist()) == [1.0]
+    assert sorted(L[long_].round(6).tolist())[0] == 4.0 and abs(sorted(L[long_])[1] - 2 * math.pi * 3) < 0.1
+    # in units of a domain of 32 cells per axis = 1: the circle is about 0.59 of it
+    assert len(lines_by_length(C, 0.5, 1.0, scale=1.0 / 32)) == 1
+    count, total = length_histogram(C, [0.0, 2.0, 5.0, 50.0])
+    assert count.tolist() == [1, 1, 1] and abs(total.sum() - L.sum()) < 1e-12
+    # bins are half-open: a length equal to an edge belongs to the bin above it
+    count, _ = length_histogram(C, [0.0, float(L[short][0]), 100.0])
+    assert count.tolist() == [0, 3]
