@@ -145,6 +145,9 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
     // are wavefronts; otherwise nobody touches the counter
     if constexpr (BATCH) more = more && s_cstart[nframes] > nwaves;
     else more = more && (n_items + chunk - 1) / chunk > nwaves;
+    // a list of at most two chunks per wavefront: the second is the wavefront's by number as well, so
+    // that thousands of wavefronts finishing their first chunk together do not queue on the counter
+    bool second_static = !BATCH && (n_items + chunk - 1) / chunk <= 2 * nwaves;
 
     int phase = PH_IDLE, mode = MODE_DESCENT;
     int fr = 0;  // frame of this lane's sample
@@ -172,10 +175,16 @@ __global__ __launch_bounds__(REF_THREADS) void refine_k(RefArgs A, const vx_ref_
         const uint64_t idle = __ballot(phase == PH_IDLE);
         const int n_idle = __popcll(idle);
         if (next >= end && more && (n_idle >= refill_min || n_idle == 64)) {
-            unsigned long long c = 0;
-            if ((tid & 63) == 0) c = atomicAdd(A.chunks, 1ull);
-            claim((int64_t)nwaves + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c >> 32)) << 32) |
-                                              __builtin_amdgcn_readfirstlane((uint32_t)c)));
+            if (second_static) {
+                second_static = false;
+                claim(wave + nwaves);
+                more = false;
+            } else {
+                unsigned long long c = 0;
+                if ((tid & 63) == 0) c = atomicAdd(A.chunks, 1ull);
+                claim((int64_t)nwaves + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c >> 32)) << 32) |
+                                                  __builtin_amdgcn_readfirstlane((uint32_t)c)));
+            }
         }
         if (next < end && (n_idle >= refill_min || n_idle == 64)) {
             if (phase == PH_IDLE) {
