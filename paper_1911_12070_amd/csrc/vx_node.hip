@@ -40,8 +40,8 @@ struct NodeArgs {
 // Output byte of a node from its three biased ring sums (each 0..8, 4 = zero circulation):
 // bits 1:0 |C| / 2 pi of the plane with the largest |C| (ties: lowest axis), bit 2 its sign
 // (1 = negative), bits 4:3 that plane's normal axis, bit 6 = vortex node (|C| > pi). 0 if all zero.
-__device__ uint8_t lut_entry(int e) {
-    const int s[3] = {e % 9 - 4, (e / 9) % 9 - 4, e / 81 - 4};
+__device__ uint8_t node_byte(int sx, int sy, int sz) {
+    const int s[3] = {sx - 4, sy - 4, sz - 4};
     int best = 0;
     for (int a = 1; a < 3; ++a)
         if (abs(s[a]) > abs(s[best])) best = a;
@@ -49,6 +49,8 @@ __device__ uint8_t lut_entry(int e) {
     if (mag == 0) return 0;
     return (uint8_t)(mag | (v < 0 ? 4 : 0) | (best << 3) | 0x40);
 }
+// the table of node_circ_k: index Sx + 9 Sy + 81 Sz
+__device__ uint8_t lut_entry(int e) { return node_byte(e % 9, (e / 9) % 9, e / 81); }
 
 // The same byte for the wide kernel's index Sx | Sz << 4 | Sy << 8 (index values with a sum above 8
 // never occur; their entries are 0)
@@ -56,7 +58,7 @@ constexpr int LUTW = 9 << 8;
 __device__ uint8_t lutw_entry(int e) {
     const int sx = e & 15, sz = (e >> 4) & 15, sy = e >> 8;
     if (sx > 8 || sz > 8 || sy > 8) return 0;
-    return lut_entry(sx + 9 * sy + 81 * sz);
+    return node_byte(sx, sy, sz);
 }
 
 // biased windings w + 1 of field a (bits 2a+1:2a of each byte) of four packed bytes
