@@ -135,13 +135,13 @@ def bench_surrogate(ex):
     import numpy as np
 
     import vxinputs
-    from paper_1911_12070_amd import vx_mlp_create, vx_mlp_destroy, vx_mlp_load
+    from paper_1911_12070_amd import MLP_NPARAMS, vx_mlp_create, vx_mlp_destroy, vx_mlp_load
     from paper_1911_12070_amd.surrogate import evaluate
     path = os.path.join(ROOT, "paper_1911_12070_amd", "weights", "surrogate_c2.bin")
     if not os.path.exists(path):
         return None
     print("[bench] surrogate vs plain refinement on the 512^3 tangle", file=sys.stderr, flush=True)
-    m = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    m = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
     vx_mlp_load(ex.h, m, path)
     r = evaluate(ex, m, vxinputs.tangle_512(), 0.9)
     vx_mlp_destroy(ex.h, m)

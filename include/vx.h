@@ -242,8 +242,9 @@ vx_status vx_refine_noalloc(vx_dims dims, const void *d_psi, const uint64_t *d_c
  * Network: inputs f (128) from the 4x4x4 patch of nodes around a cell (offsets -1..2 on each
  * axis from the min corner; patch node q = a + 4b + 16c, x fastest): f[2q] = Re psi_q / s,
  * f[2q+1] = Im psi_q / s, s = sqrt(mean_q |psi_q|^2) (s = 1 if zero). Z1 = f W1 + b1,
- * H1 = gelu(Z1), Z2 = H1 W2 + b2, H2 = gelu(Z2), Z3 = H2 W3 + b3 with W1 128x256, W2 256x256,
- * W3 256x4 (row index = input), gelu(x) = x (1 + erf(x / sqrt 2)) / 2. Outputs: Z3[0..2] = the
+ * H1 = gelu(Z1), Z2 = H1 W2 + b2, H2 = gelu(Z2), Z3 = H2 W3 + b3 with W1 128xH, W2 HxH, W3 Hx4
+ * (row index = input; hidden width H = VX_MLP_NHID = 128), gelu(x) = x (1 + erf(x / sqrt 2)) / 2.
+ * Outputs: Z3[0..2] = the
  * core sample minus the cell's first estimate x0 (mean of its pierced-face centres, cell units);
  * conf = 1 / (1 + exp(-Z3[3])).
  * Arithmetic: BF16 matrix operands (features, weights, activations) on the matrix cores with FP32
@@ -256,9 +257,9 @@ vx_status vx_refine_noalloc(vx_dims dims, const void *d_psi, const uint64_t *d_c
  * over the minibatch is minimised with Adam.
  * ---------------------------------------------------------------------------------------- */
 #define VX_MLP_NIN 128
-#define VX_MLP_NHID 256
+#define VX_MLP_NHID 128
 #define VX_MLP_NOUT 4
-#define VX_MLP_NPARAMS 99844
+#define VX_MLP_NPARAMS 33540
 #define VX_SAMPLE_SURROGATE 128u  /* position from the surrogate network + one Newton step */
 
 typedef struct vx_mlp vx_mlp;
@@ -269,7 +270,7 @@ typedef struct {
 } vx_adam_params;
 
 /* h_params: VX_MLP_NPARAMS initial values (host memory, copied). max_batch: largest minibatch of
- * the training calls (their scratch, about 3 KiB per row, is allocated here). */
+ * the training calls (their scratch, about 1.5 KiB per row, is allocated here). */
 vx_status vx_mlp_create(vx_handle *h, const float *h_params, int64_t max_batch, vx_mlp **out);
 vx_status vx_mlp_destroy(vx_mlp *m);
 /* Reserve the inference buffers of vx_mlp_infer for lists of up to max_cells cells (98 bytes per

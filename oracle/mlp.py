@@ -8,7 +8,8 @@ confidence. Every step is written out from its definition:
              corner, x fastest); s = sqrt(mean_q |psi_q|^2) (s = 1 if the patch is all zero);
              f[2q] = Re psi_q / s, f[2q+1] = Im psi_q / s                      (128 inputs)
   network    Z1 = X W1 + b1, H1 = gelu(Z1), Z2 = H1 W2 + b2, H2 = gelu(Z2), Z3 = H2 W3 + b3,
-             W1: 128x256, W2: 256x256, W3: 256x4 (rows = inputs); gelu(x) = x Phi(x) with
+             W1: 128xH, W2: HxH, W3: Hx4 (rows = inputs; the hidden width H, 128 in the library,
+             is read from the parameters); gelu(x) = x Phi(x) with
              Phi(x) = (1 + erf(x / sqrt 2)) / 2 (erf from the platform's math library)
   outputs    delta = Z3[:, 0:3] (predicted x* - x0, cell units), conf = sigmoid(Z3[:, 3])
   loss       mean over the batch of  |delta - t|^2 + lam * bce(Z3[:, 3], y),

@@ -40,7 +40,8 @@ EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status
            "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_infer",
            "vx_profile_enable", "vx_profile_read"]
 
-MLP_NPARAMS = 99844
+MLP_NHID = 128
+MLP_NPARAMS = 128 * MLP_NHID + MLP_NHID + MLP_NHID * MLP_NHID + MLP_NHID + MLP_NHID * 4 + 4  # 33540
 SAMPLE_SURROGATE = 128
 
 BATCH_MAX_FRAMES = 128

@@ -1,4 +1,4 @@
-// Surrogate of the core-sample refinement: a 128-256-256-4 GELU network that maps the 4x4x4 psi
+// Surrogate of the core-sample refinement: a 128-NH-NH-4 GELU network (NH = VX_MLP_NHID) that maps the 4x4x4 psi
 // patch of a pierced cell to the offset of its refined core sample from the first estimate (the
 // mean of the pierced-face centres, Sec. 3.3.1) plus a confidence. Training data are produced by
 // the plain refinement (Sec. 3.3.3); below the confidence threshold the plain refinement runs.
@@ -6,9 +6,9 @@
 // Matrix cores. The two hidden layers are BF16 products with FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16: lane l of a wavefront holds row (l % 16) of a 16x32 A block and column
 // (l % 16) of a 32x16 B block, k = 8 (l / 16) .. +7 as eight BF16 values; the 16x16 FP32 result
-// holds rows 4 (l / 16) + i, column l % 16 in its four registers. A workgroup (4 wavefronts) owns a
-// tile of 64 rows; wavefront w computes columns 64w .. 64w+63 of a layer for all 64 rows (4 x 4
-// blocks). A operands come from LDS (row pitch padded by 8 values so that the 16 rows of a block
+// holds rows 4 (l / 16) + i, column l % 16 in its four registers. A training workgroup (4 wavefronts)
+// owns a tile of 64 rows; wavefront w computes columns NH/4 w .. NH/4 (w+1) - 1 of a layer for all 64
+// rows (4 x NH/64 blocks). A operands come from LDS (row pitch padded by 8 values so that the 16 rows of a block
 // fall on different banks), B operands are read as 16-byte vectors from transposed BF16 weight
 // copies (k contiguous), which stay in L2.
 // The 4-wide head runs on the matrix cores too (N padded to 16); its gradients, the bias
@@ -42,6 +42,10 @@ static_assert(NPARAM == VX_MLP_NPARAMS, "parameter count");
 
 constexpr int TM = 64;           // rows per tile
 constexpr int NT = 256;          // threads per workgroup
+constexpr int WFT = NH / 4;      // hidden features per wavefront in the training kernels (4 wavefronts)
+constexpr int NCB = WFT / 16;    // their 16-column blocks
+static_assert(NH == 128 || NH == 256,
+              "hidden width 128 or 256: 128-column weight-gradient blocks, one bwd_rows_k thread per column");
 constexpr int POLISH_WG_PER_CU = 5;  // polish workgroups per CU (what fits at its 87 VGPRs)
 constexpr int XP = NIN + 8;      // LDS row pitch (values) of the input tile
 constexpr int HP = NH + 8;       // LDS row pitch of a hidden tile
@@ -212,26 +216,26 @@ __device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const f
 
 // ---------------------------------------------------------------------------- layer building blocks
 
-// acc = A (64 x K, LDS, pitch AP) times B (K x 64: columns n0 .. n0+63 of a K-contiguous weight
-// copy Wt[col][k]) for this wavefront
-template <int K, int AP>
-__device__ __forceinline__ void layer(const __bf16 *sA, const __bf16 *__restrict__ Wt, int n0, f32x4 acc[4][4]) {
+// acc = A (64 x K, LDS, pitch AP) times B (K x 16 NC: columns n0 .. n0 + 16 NC - 1 of a K-contiguous
+// weight copy Wt[col][k]) for this wavefront
+template <int K, int AP, int NC>
+__device__ __forceinline__ void layer(const __bf16 *sA, const __bf16 *__restrict__ Wt, int n0, f32x4 acc[4][NC]) {
     const int l = threadIdx.x & 63;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < NC; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 b[4], a[4];
+        bf16x8 b[NC], a[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = ld8(Wt + (size_t)(n0 + 16 * c + (l & 15)) * K + k0 + 8 * (l >> 4));
+        for (int c = 0; c < NC; ++c) b[c] = ld8(Wt + (size_t)(n0 + 16 * c + (l & 15)) * K + k0 + 8 * (l >> 4));
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = ld8(sA + (16 * r + (l & 15)) * AP + k0 + 8 * (l >> 4));
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
+            for (int c = 0; c < NC; ++c) acc[r][c] = mfma(a[r], b[c], acc[r][c]);
     }
 }
 
@@ -251,10 +255,10 @@ __device__ __forceinline__ f32x4 head(const __bf16 *sH, const __bf16 *__restrict
 
 struct Net {  // device copies used by the kernels
     const float *master;  // FP32 parameters (host layout)
-    const __bf16 *w1t;    // [256][128]  W1 transposed
-    const __bf16 *w2t;    // [256][256]  W2 transposed
-    const __bf16 *w2c;    // [256][256]  W2 as is (rows = inputs): B operand of dH1 = dZ2 W2^T
-    const __bf16 *w3t;    // [16][256]   W3 transposed, rows 4..15 zero
+    const __bf16 *w1t;    // [NH][NIN]  W1 transposed
+    const __bf16 *w2t;    // [NH][NH]   W2 transposed
+    const __bf16 *w2c;    // [NH][NH]   W2 as is (rows = inputs): B operand of dH1 = dZ2 W2^T
+    const __bf16 *w3t;    // [16][NH]   W3 transposed, rows 4..15 zero
     const float2 *gelu;   // [GT] (value, step)
     const float2 *dgelu;  // [GT] (derivative, step)
 };
@@ -272,11 +276,11 @@ __device__ __forceinline__ void load_tables(const Net &N, float2 *sg, float2 *sd
 __device__ __forceinline__ void hidden(const Net &N, const __bf16 *sX, __bf16 *sH, const float2 *sg, const float2 *sd,
                                        int64_t row0, int64_t nrows, __bf16 *H1, __bf16 *G1, __bf16 *H2, __bf16 *G2) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int n0 = 64 * w;
-    f32x4 acc[4][4];
-    layer<NIN, XP>(sX, N.w1t, n0, acc);
+    const int n0 = WFT * w;
+    f32x4 acc[4][NCB];
+    layer<NIN, XP, NCB>(sX, N.w1t, n0, acc);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCB; ++c) {
         const int col = n0 + 16 * c + (l & 15);
         const float bias = N.master[OFF_B1 + col];
 #pragma unroll
@@ -294,10 +298,10 @@ __device__ __forceinline__ void hidden(const Net &N, const __bf16 *sX, __bf16 *s
             }
     }
     __syncthreads();
-    layer<NH, HP>(sH, N.w2t, n0, acc);
+    layer<NH, HP, NCB>(sH, N.w2t, n0, acc);
     __syncthreads();  // every wavefront has read H1
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCB; ++c) {
         const int col = n0 + 16 * c + (l & 15);
         const float bias = N.master[OFF_B2 + col];
 #pragma unroll
@@ -440,7 +444,7 @@ __global__ __launch_bounds__(NT) void bwd_rows_k(Net N, int64_t n, const float *
     for (int e = t; e < NH * NOUT; e += NT) sW3[e] = N.master[OFF_W3 + e];
     __syncthreads();
     // column t: dH2 = dZ3 W3^T, dZ2 = dH2 gelu'(Z2); gradients of b2, W3 row t; b3
-    {
+    if (t < NH) {
         const int o = t;
         float db2 = 0.f, gw[NOUT] = {0.f, 0.f, 0.f, 0.f};
         for (int r = 0; r < TM; ++r) {
@@ -470,11 +474,11 @@ __global__ __launch_bounds__(NT) void bwd_rows_k(Net N, int64_t n, const float *
     }
     __syncthreads();
     // dH1 = dZ2 W2^T on the matrix cores; dZ1 = dH1 gelu'(Z1); gradient of b1
-    const int l = t & 63, w = t >> 6, n0 = 64 * w;
-    f32x4 acc[4][4];
-    layer<NH, HP>(sD, N.w2c, n0, acc);
+    const int l = t & 63, w = t >> 6, n0 = WFT * w;
+    f32x4 acc[4][NCB];
+    layer<NH, HP, NCB>(sD, N.w2c, n0, acc);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCB; ++c) {
         const int col = n0 + 16 * c + (l & 15);
         float db1 = 0.f;
 #pragma unroll
@@ -661,20 +665,22 @@ __global__ __launch_bounds__(NT) void dataset_k(Geo g, const uint64_t *__restric
 }
 
 constexpr int NK1 = NIN / 32, NK2 = NH / 32;  // k-steps of the two hidden layers
-constexpr int NTI = 512;                        // inference workgroup: 8 wavefronts
+constexpr int NTI = 2 * NH;                     // inference workgroup: NH / 32 wavefronts of 32 features
+constexpr int GPC = NTI / TM;                   // gather threads per cell
+constexpr int RPT = 16 / GPC;                   // patch rows (4 nodes each) per gather thread
 
 // Workgroup barrier for LDS traffic only: this wavefront's LDS operations are complete, global loads
 // may still be in flight (they land in registers that are not read before their own wait).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Inference, part 1: the network for every listed cell. Persistent: one workgroup of 8 wavefronts
-// per CU walks the 64-cell tiles; wavefront w owns features 32w .. 32w+31 of both hidden layers and
-// keeps their B operands in registers for the whole run (24 16-byte fragments) instead of loading
-// them per tile. The layers are computed transposed, (X W)^T = W^T X^T, so that a lane ends with
+// Inference, part 1: the network for every listed cell. Persistent: workgroups of NH / 32 wavefronts,
+// as many per CU as fit, walk the 64-cell tiles; wavefront w owns features 32w .. 32w+31 of both
+// hidden layers and keeps their B operands in registers for the whole run (NIN / 16 + NH / 16 + 1
+// 16-byte fragments) instead of loading them per tile. The layers are computed transposed, (X W)^T = W^T X^T, so that a lane ends with
 // four consecutive features of one cell: they go to LDS as one 8-byte word (first layer) or, after
 // the second layer, straight into a B operand of the head, whose k index is permuted to match
 // (k = 8q + j holds feature 32w + 4q + j for j < 4 and 32w + 16 + 4q + j - 4 otherwise, q = lane / 16).
-// Each wavefront thus multiplies its own 32 features by the matching rows of W3 and the eight
+// Each wavefront thus multiplies its own 32 features by the matching rows of W3 and the NH / 32
 // partial heads of a cell are summed in LDS, by wavefront 0 after the next tile's first barrier: two
 // barriers per tile (features, first layer).
 // The barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell
@@ -683,6 +689,7 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
                                                    const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
                                                    float4 *centre, int64_t *fb_count, unsigned long long *flag) {
     constexpr int NW = NTI / 64;
+    static_assert(NW * 32 == NH && (GPC == 4 || GPC == 8), "one wavefront per 32 hidden features");
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
     __shared__ float2 sg[GT];
@@ -716,29 +723,31 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
     }
     const float4 bias3 = make_float4(N.master[OFF_B3], N.master[OFF_B3 + 1], N.master[OFF_B3 + 2], N.master[OFF_B3 + 3]);
 
-    // gather role: eight threads per cell; thread (r, pc, hb) loads rows 2hb, 2hb+1 of patch plane pc
-    const int r = t >> 3, pc = (t >> 1) & 3, hb = t & 1;
+    // gather role: GPC threads per cell; thread (r, q) loads patch rows q RPT .. q RPT + RPT - 1 (row R:
+    // row R % 4 of patch plane R / 4), i.e. features 8 RPT q .. 8 RPT (q + 1) - 1
+    const int r = t / GPC, q = t % GPC;
     const uint64_t ncell = (uint64_t)g.nx * g.ny * g.nz;
     auto cell_of = [&](int64_t tile) -> uint64_t {
         const int64_t s = tile * TM + r;
         const uint64_t c = (tile < ntiles && s < n) ? cells[s] : 0;
         return c < ncell ? c : 0;
     };
-    float2 v[8];
+    float2 v[4 * RPT];
     auto fetch = [&](uint64_t cell) {
         int i, j, k;
         cell_xyz(cell, g, i, j, k);
-        const int kk = wrapc(k + pc - 1, g.nz, g.pz);
         const uint64_t nx = (uint64_t)g.nx;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int jj = wrapc(j + 2 * hb + b - 1, g.ny, g.py);
+        for (int b = 0; b < RPT; ++b) {
+            const int R = q * RPT + b;
+            const int kk = wrapc(k + (R >> 2) - 1, g.nz, g.pz);
+            const int jj = wrapc(j + (R & 3) - 1, g.ny, g.py);
             const float2 *row = g.psi + nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk);
 #pragma unroll
             for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
         }
     };
-    // output of tile tt (if it is one of this workgroup's tiles): bias + the eight partial heads
+    // output of tile tt (if it is one of this workgroup's tiles): bias + the NW partial heads
     auto head_out = [&](int64_t tt) {
         if (tt >= (int64_t)blockIdx.x && t < TM && tt * TM + t < n) {
             float4 o = bias3;
@@ -761,22 +770,26 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
         {
             float ss = 0.f;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) ss += v[q].x * v[q].x + v[q].y * v[q].y;
-            ss += __shfl_xor(ss, 1);
-            ss += __shfl_xor(ss, 2);
-            ss += __shfl_xor(ss, 4);
-            const float is = 1.f / (ss > 0.f ? sqrtf(ss * (1.f / 64.f)) : 1.f);
-            uint32_t *dst = (uint32_t *)(sX + r * XP + 32 * pc + 16 * hb);
+            for (int e = 0; e < 4 * RPT; ++e) ss += v[e].x * v[e].x + v[e].y * v[e].y;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) dst[q] = pack2(v[q].x * is, v[q].y * is);
+            for (int o = 1; o < GPC; o <<= 1) ss += __shfl_xor(ss, o);
+            const float is = 1.f / (ss > 0.f ? sqrtf(ss * (1.f / 64.f)) : 1.f);
+            uint32_t *dst = (uint32_t *)(sX + r * XP + 8 * RPT * q);
+#pragma unroll
+            for (int e = 0; e < 4 * RPT; ++e) dst[e] = pack2(v[e].x * is, v[e].y * is);
             // the cell's own corners d = dx + 2 dy + 4 dz (nodes 1, 2 of rows 1, 2 of planes 1, 2) for
-            // the polish: row 1 is this thread's second row if hb = 0, row 2 its first if hb = 1
-            // (streaming stores: read once, by the next kernel)
+            // the polish, from the threads that hold those rows: corners 2 (dy + 2 dz) and 2 (dy + 2 dz) + 1
+            // as one float4 (streaming stores: read once, by the next kernel)
             const int64_t s = tile * TM + r;
-            if ((pc == 1 || pc == 2) && s < n) {
+            if (s < n) {
                 typedef float f4v __attribute__((ext_vector_type(4)));
-                const float2 c0 = hb ? v[1] : v[5], c1 = hb ? v[2] : v[6];
-                __builtin_nontemporal_store((f4v){c0.x, c0.y, c1.x, c1.y}, (f4v *)(centre + 4 * s + hb + 2 * (pc - 1)));
+#pragma unroll
+                for (int b = 0; b < RPT; ++b) {
+                    const int R = q * RPT + b, pz = R >> 2, py = R & 3;
+                    if (pz >= 1 && pz <= 2 && py >= 1 && py <= 2)
+                        __builtin_nontemporal_store((f4v){v[4 * b + 1].x, v[4 * b + 1].y, v[4 * b + 2].x, v[4 * b + 2].y},
+                                                    (f4v *)(centre + 4 * s + 2 * (pz - 1) + (py - 1)));
+                }
             }
         }
         // next tile's nodes and the ids of the one after, in flight while this tile's layers run
@@ -940,6 +953,7 @@ struct vx_mlp {
     uint16_t *fb_desc = nullptr;
     int64_t *fb_index = nullptr;
     int64_t *fb_count = nullptr;
+    int infer_per_cu = 1;  // resident infer_net_k workgroups per CU
     std::vector<void *> allocs;
 };
 
@@ -1050,6 +1064,11 @@ extern "C" vx_status vx_mlp_create(vx_handle *h, const float *h_params, int64_t 
         st = refresh(m, 0);
     }
     if (st == VX_OK) st = vx_hip_check(h, hipDeviceSynchronize(), "vx_mlp_create");
+    if (st == VX_OK) {
+        int nb = 0;
+        st = vx_hip_check(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, infer_net_k, NTI, 0), "vx_mlp_create");
+        m->infer_per_cu = nb > 0 ? nb : 1;
+    }
     if (st) {
         vx_mlp_destroy(m);
         return st;
@@ -1255,7 +1274,7 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
     vx_timer tm(h, hs, VX_KIND_MLP);
     const int64_t num_cu = h->num_cu > 0 ? h->num_cu : 256;
     const int64_t tiles = (cap + TM - 1) / TM;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu * m->infer_per_cu));
     hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
                        d_count, cap, m->net_out, m->centre, m->fb_count, vx_overflow_flag(h));
     tm.stop();

@@ -23,7 +23,7 @@ import time
 
 import numpy as np
 
-from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_MAX_STEP, SAMPLE_SURROGATE, AdamParams, Extractor, dims,
+from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_MAX_STEP, MLP_NPARAMS, SAMPLE_SURROGATE, AdamParams, Extractor, dims,
                samples_to_numpy, vx_mlp_create, vx_mlp_dataset, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
                vx_mlp_reserve, vx_mlp_save, vx_mlp_train_step, vx_profile_enable, vx_profile_read)
 
@@ -195,7 +195,7 @@ def main(argv=None):
         print(json.dumps(res))
         vx_mlp_destroy(ex.h, m)
     else:
-        m = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+        m = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
         vx_mlp_load(ex.h, m, args.weights)
         print(json.dumps(evaluate(ex, m, vxinputs.tangle_512(), args.threshold)))
         vx_mlp_destroy(ex.h, m)

@@ -105,7 +105,7 @@ def test_c5_tangle_512_plain_and_surrogate():
     import os
 
     import torch
-    from paper_1911_12070_amd import (SAMPLE_SURROGATE, Extractor, dims, samples_to_numpy, vx_mlp_create,
+    from paper_1911_12070_amd import (MLP_NPARAMS, SAMPLE_SURROGATE, Extractor, dims, samples_to_numpy, vx_mlp_create,
                                       vx_mlp_destroy, vx_mlp_infer, vx_mlp_load, vx_mlp_reserve)
     ex = Extractor(0)
     try:
@@ -114,7 +114,7 @@ def test_c5_tangle_512_plain_and_surrogate():
         out, psi_h, cells, cdesc, R = run_single(ex, psi, 7, "C5 tangle_512", cap)
         nc = len(cells)
         weights = os.path.join(os.path.dirname(__file__), "..", "paper_1911_12070_amd", "weights", "surrogate_c2.bin")
-        m = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+        m = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
         vx_mlp_reserve(ex.h, m, cap)
         vx_mlp_load(ex.h, m, weights)
         sur = ex.alloc_samples(cap)

@@ -28,7 +28,7 @@ WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_1911_12070_amd", 
 
 def test_trained_surrogate_gain():
     import torch
-    from paper_1911_12070_amd import (KIND_MLP, KIND_POLISH, KIND_REFINE, SAMPLE_SURROGATE, Extractor, dims,
+    from paper_1911_12070_amd import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_NPARAMS, SAMPLE_SURROGATE, Extractor, dims,
                                       samples_to_numpy, vx_mlp_create, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
                                       vx_mlp_reserve,
                                       vx_profile_enable, vx_profile_read)
@@ -61,11 +61,11 @@ def test_trained_surrogate_gain():
     P = samples_to_numpy(plain, nc)
     good = (P["status"] & (8 | 16 | 32 | 64)) == 0
 
-    zero = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    zero = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
     vx_mlp_reserve(ex.h, zero, cap)
     z = ex.alloc_samples(cap)
     vx_mlp_infer(ex.h, zero, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, 0.0, z, max_step=0.0)
-    trained = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+    trained = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
     vx_mlp_reserve(ex.h, trained, cap)
     vx_mlp_load(ex.h, trained, WEIGHTS)
     a = ex.alloc_samples(cap)

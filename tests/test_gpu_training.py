@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 def test_training_from_scratch_beats_the_zero_network():
     import torch
-    from paper_1911_12070_amd import (SAMPLE_SURROGATE, Extractor, dims, samples_to_numpy, vx_mlp_create,
+    from paper_1911_12070_amd import (MLP_NPARAMS, SAMPLE_SURROGATE, Extractor, dims, samples_to_numpy, vx_mlp_create,
                                       vx_mlp_destroy, vx_mlp_infer, vx_mlp_reserve)
     from paper_1911_12070_amd.surrogate import build_dataset, train
     ex = Extractor(0)
@@ -42,7 +42,7 @@ def test_training_from_scratch_beats_the_zero_network():
         nc = int(out["counts"][1])
         cap = out["cells"].numel()
         P = samples_to_numpy(plain, nc)
-        zero = vx_mlp_create(ex.h, np.zeros(99844, np.float32), 64)
+        zero = vx_mlp_create(ex.h, np.zeros(MLP_NPARAMS, np.float32), 64)
         errs = {}
         for name, net in (("zero", zero), ("trained", m)):
             vx_mlp_reserve(ex.h, net, cap)

@@ -241,8 +241,9 @@ def random_small_int_field(dims, seed: int, lo: int = -2, hi: int = 2) -> np.nda
 # Surrogate network: initial weights and the flat parameter layout
 # ----------------------------------------------------------------------------------------------
 
-MLP_SHAPES = (("W1", (128, 256)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (256, 4)),
-              ("b3", (4,)))
+MLP_NHID = 128  # hidden width
+MLP_SHAPES = (("W1", (128, MLP_NHID)), ("b1", (MLP_NHID,)), ("W2", (MLP_NHID, MLP_NHID)), ("b2", (MLP_NHID,)),
+              ("W3", (MLP_NHID, 4)), ("b3", (4,)))
 MLP_NPARAMS = sum(int(np.prod(s)) for _, s in MLP_SHAPES)
 
 
