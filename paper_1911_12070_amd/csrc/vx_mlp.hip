@@ -737,14 +737,25 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
         int i, j, k;
         cell_xyz(cell, g, i, j, k);
         const uint64_t nx = (uint64_t)g.nx;
+        // away from the x seams a row's four nodes are contiguous: two 16-byte loads (8-byte aligned)
+        const bool xin = i >= 1 && i + 2 < g.nx;
 #pragma unroll
         for (int b = 0; b < RPT; ++b) {
             const int R = q * RPT + b;
             const int kk = wrapc(k + (R >> 2) - 1, g.nz, g.pz);
             const int jj = wrapc(j + (R & 3) - 1, g.ny, g.py);
             const float2 *row = g.psi + nx * ((uint64_t)jj + (uint64_t)g.ny * (uint64_t)kk);
+            if (xin) {
+                typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+                const f4a8 lo = *(const f4a8 *)(row + i - 1), hi = *(const f4a8 *)(row + i + 1);
+                v[4 * b + 0] = make_float2(lo.x, lo.y);
+                v[4 * b + 1] = make_float2(lo.z, lo.w);
+                v[4 * b + 2] = make_float2(hi.x, hi.y);
+                v[4 * b + 3] = make_float2(hi.z, hi.w);
+            } else {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
+                for (int a = 0; a < 4; ++a) v[4 * b + a] = row[wrapc(i + a - 1, g.nx, g.px)];
+            }
         }
     };
     // output of tile tt (if it is one of this workgroup's tiles): bias + the NW partial heads
@@ -860,13 +871,15 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 
 // Inference, part 2: one thread per listed cell. Confident single-core interior cells get the
 // network's point polished by one Newton step; the others, and cells whose polish fails, are queued
-// (cell, descriptor, position in the list) for the plain refinement, with one atomic per wavefront.
+// (cell, descriptor, position in the list) for the plain refinement, with one atomic per workgroup and pass.
 __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict__ cells,
                                                const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
                                                int64_t cap, const float4 *__restrict__ net_out,
                                                const float4 *__restrict__ centre, float thr, float max_step,
                                                vx_sample *out, uint64_t *fb_cell, uint16_t *fb_desc, int64_t *fb_index,
                                                int64_t *fb_count) {
+    __shared__ uint32_t s_cnt;
+    __shared__ int64_t s_base;
     const int64_t n = min(*count, cap);
     // grid-stride over the listed cells: the grid is sized for the capacity only up to what the chip
     // holds at once, so that a short list does not pay for thousands of workgroups that find nothing
@@ -913,21 +926,30 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
             }
             queue = !mine;
         }
+        // the workgroup's queued cells take one block of the queue: the wavefronts count theirs in LDS
+        // and one thread reserves the block with a single atomic (device-scope atomics on one counter
+        // are serialised; one per wavefront made the queue the bottleneck of this kernel)
         const uint64_t qm = __ballot(queue);
+        const int lane = (int)(threadIdx.x & 63);
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        uint32_t woff = 0;
         if (qm) {
             const int lead = __builtin_ctzll(qm);
-            unsigned long long base = 0;
-            if ((int)(threadIdx.x & 63) == lead)
-                base = atomicAdd((unsigned long long *)fb_count, (unsigned long long)__popcll(qm));
-            base = ((unsigned long long)(uint32_t)__shfl((int)(base >> 32), lead) << 32) | (uint32_t)__shfl((int)base, lead);
-            if (queue) {
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-                const int64_t k = (int64_t)base + rank;
-                fb_cell[k] = cell;
-                fb_desc[k] = (uint16_t)d;
-                fb_index[k] = s;
-            }
+            if (lane == lead) woff = atomicAdd(&s_cnt, (uint32_t)__popcll(qm));
+            woff = (uint32_t)__shfl((int)woff, lead);
         }
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) s_base = (int64_t)atomicAdd((unsigned long long *)fb_count, (unsigned long long)s_cnt);
+        __syncthreads();
+        if (queue) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+            const int64_t k = s_base + woff + rank;
+            fb_cell[k] = cell;
+            fb_desc[k] = (uint16_t)d;
+            fb_index[k] = s;
+        }
+        __syncthreads();  // s_cnt and s_base are reset and rewritten by the next iteration
     }
 }
 
