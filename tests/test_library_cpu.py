@@ -29,6 +29,28 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) <= set(vx.EXPORTS)
 
 
+def test_network_size_constants_agree():
+    """The surrogate's sizes in the header, the binding, the seeded initial weights and the committed
+    weights file describe one network: 128 inputs, hidden width H, 4 outputs."""
+    import numpy as np
+
+    import paper_1911_12070_amd as vx
+    import vxinputs
+    text = open(os.path.join(ROOT, "include", "vx.h")).read()
+    c = {k: int(v) for k, v in re.findall(r"#define VX_MLP_(NIN|NHID|NOUT|NPARAMS) (\d+)", text)}
+    nin, h, nout = c["NIN"], c["NHID"], c["NOUT"]
+    assert c["NPARAMS"] == nin * h + h + h * h + h + h * nout + nout
+    assert vx.MLP_NHID == h and vx.MLP_NPARAMS == c["NPARAMS"]
+    assert vxinputs.MLP_NHID == h and vxinputs.MLP_NPARAMS == c["NPARAMS"]
+    assert vxinputs.mlp_pack(vxinputs.mlp_init(0)).size == c["NPARAMS"]
+    path = os.path.join(ROOT, "paper_1911_12070_amd", "weights", "surrogate_c2.bin")
+    raw = open(path, "rb").read()
+    assert raw[:6] == b"VXMLP1"
+    assert int(np.frombuffer(raw[8:16], np.int64)[0]) == c["NPARAMS"] and len(raw) == 16 + 4 * c["NPARAMS"]
+    w = np.frombuffer(raw[16:], np.float32)
+    assert np.isfinite(w).all() and np.abs(w).max() > 0
+
+
 def test_status_strings_and_defaults():
     import paper_1911_12070_amd as vx
     lib = vx.lib()
