@@ -1,18 +1,17 @@
-// Surrogate of the core-sample refinement: a 128-NH-NH-4 GELU network (NH = VX_MLP_NHID) that maps the 4x4x4 psi
-// patch of a pierced cell to the offset of its refined core sample from the first estimate (the
-// mean of the pierced-face centres, Sec. 3.3.1) plus a confidence. Training data are produced by
-// the plain refinement (Sec. 3.3.3); below the confidence threshold the plain refinement runs.
+// Surrogate of the core-sample refinement: a 128-NH-NH-4 GELU network (NH = VX_MLP_NHID) that maps the 4x4x4
+// psi patch of a pierced cell to the offset of its refined core sample from the first estimate (the mean of
+// the pierced-face centres, Sec. 3.3.1) plus a confidence. Training data are produced by the plain refinement
+// (Sec. 3.3.3); below the confidence threshold the plain refinement runs.
 //
 // Matrix cores. The two hidden layers are BF16 products with FP32 accumulation on
 // v_mfma_f32_16x16x32_bf16: lane l of a wavefront holds row (l % 16) of a 16x32 A block and column
 // (l % 16) of a 32x16 B block, k = 8 (l / 16) .. +7 as eight BF16 values; the 16x16 FP32 result
-// holds rows 4 (l / 16) + i, column l % 16 in its four registers. A training workgroup (4 wavefronts)
-// owns a tile of 64 rows; wavefront w computes columns NH/4 w .. NH/4 (w+1) - 1 of a layer for all 64
-// rows (4 x NH/64 blocks). A operands come from LDS (row pitch padded by 8 values so that the 16 rows of a block
-// fall on different banks), B operands are read as 16-byte vectors from transposed BF16 weight
-// copies (k contiguous), which stay in L2.
-// The 4-wide head runs on the matrix cores too (N padded to 16); its gradients, the bias
-// gradients and the loss are small reductions done on the vector ALUs.
+// holds rows 4 (l / 16) + i, column l % 16 in its four registers. A training workgroup (4 wavefronts) owns a
+// tile of 64 rows; wavefront w computes columns NH/4 w .. NH/4 (w+1) - 1 of a layer for all 64 rows (4 x
+// NH/64 blocks). A operands come from LDS (row pitch padded by 8 values so that the 16 rows of a block fall
+// on different banks), B operands are read as 16-byte vectors from transposed BF16 weight copies (k
+// contiguous), which stay in L2. The 4-wide head runs on the matrix cores too (N padded to 16); its
+// gradients, the bias gradients and the loss are small reductions done on the vector ALUs.
 //
 // Training on a minibatch of n rows (all on the device, no host synchronisation):
 //   fwd_train_k   per 64-row tile: layers, H1/H2 and gelu'(Z1)/gelu'(Z2) to global scratch (BF16),
@@ -133,17 +132,16 @@ __device__ __forceinline__ void gather_features(const Geo &g, int i, int j, int 
     }
 }
 
-// The surrogate's final step, in the refinement's own arithmetic (the functions of vx_refine_math.h,
-// Sec. 3.3.3 reading): the network's point xs projected onto the plane through x0 normal to
-// t = grad Re psi x grad Im psi at x0, then one Newton step on (Re psi, Im psi) in that plane.
-// False where the plain refinement must run: degenerate t, singular Jacobian, a point outside the
-// patch, or -- when max_step > 0 -- a Newton step from the polished point that would be longer than
-// max_step cells (that step estimates the polished point's distance from the zero of psi in the
-// plane, so a confident but wrong prediction goes to the plain method instead of being reported).
-// The corners of the cell itself come in ctr (64 contiguous bytes written by the network kernel,
-// loaded by the caller together with its other inputs), the others from the field; those of x0's cell and of xs's cell are requested together: the
-// projected point and the Newton point mostly lie in one of the two, so that the evaluations usually
-// wait for one round of loads.
+// The surrogate's final step, in the refinement's own arithmetic (the functions of vx_refine_math.h, Sec.
+// 3.3.3 reading): the network's point xs projected onto the plane through x0 normal to t = grad Re psi x grad
+// Im psi at x0, then one Newton step on (Re psi, Im psi) in that plane. False where the plain refinement must
+// run: degenerate t, singular Jacobian, a point outside the patch, or -- when max_step > 0 -- a Newton step
+// from the polished point that would be longer than max_step cells (that step estimates the polished point's
+// distance from the zero of psi in the plane, so a confident but wrong prediction goes to the plain method
+// instead of being reported). The corners of the cell itself come in ctr (64 contiguous bytes written by the
+// network kernel, loaded by the caller together with its other inputs), the others from the field; those of
+// x0's cell and of xs's cell are requested together: the projected point and the Newton point mostly lie in
+// one of the two, so that the evaluations usually wait for one round of loads.
 __device__ bool polish(const Geo &g, int i, int j, int k, uint32_t desc, const float4 ctr[4], const vxr::V3 &x0,
                        const vxr::V3 &xs, float max_step, vxr::V3 &out, float &rho) {
     using namespace vxr;
@@ -673,18 +671,17 @@ constexpr int RPT = 16 / GPC;                   // patch rows (4 nodes each) per
 // may still be in flight (they land in registers that are not read before their own wait).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Inference, part 1: the network for every listed cell. Persistent: workgroups of NH / 32 wavefronts,
-// as many per CU as fit, walk the 64-cell tiles; wavefront w owns features 32w .. 32w+31 of both
-// hidden layers and keeps their B operands in registers for the whole run (NIN / 16 + NH / 16 + 1
-// 16-byte fragments) instead of loading them per tile. The layers are computed transposed, (X W)^T = W^T X^T, so that a lane ends with
-// four consecutive features of one cell: they go to LDS as one 8-byte word (first layer) or, after
-// the second layer, straight into a B operand of the head, whose k index is permuted to match
-// (k = 8q + j holds feature 32w + 4q + j for j < 4 and 32w + 16 + 4q + j - 4 otherwise, q = lane / 16).
-// Each wavefront thus multiplies its own 32 features by the matching rows of W3 and the NH / 32
-// partial heads of a cell are summed in LDS, by wavefront 0 after the next tile's first barrier: two
-// barriers per tile (features, first layer).
-// The barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell
-// ids of the one after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
+// Inference, part 1: the network for every listed cell. Persistent: workgroups of NH / 32 wavefronts, as many
+// per CU as fit, walk the 64-cell tiles; wavefront w owns features 32w .. 32w+31 of both hidden layers and
+// keeps their B operands in registers for the whole run (NIN / 16 + NH / 16 + 1 16-byte fragments) instead of
+// loading them per tile. The layers are computed transposed, (X W)^T = W^T X^T, so that a lane ends with four
+// consecutive features of one cell: they go to LDS as one 8-byte word (first layer) or, after the second
+// layer, straight into a B operand of the head, whose k index is permuted to match (k = 8q + j holds feature
+// 32w + 4q + j for j < 4 and 32w + 16 + 4q + j - 4 otherwise, q = lane / 16). Each wavefront thus multiplies
+// its own 32 features by the matching rows of W3 and the NH / 32 partial heads of a cell are summed in LDS,
+// by wavefront 0 after the next tile's first barrier: two barriers per tile (features, first layer). The
+// barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell ids of the one
+// after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
 __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
                                                    const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
                                                    float4 *centre, int64_t *fb_count, unsigned long long *flag) {
@@ -788,9 +785,9 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
             uint32_t *dst = (uint32_t *)(sX + r * XP + 8 * RPT * q);
 #pragma unroll
             for (int e = 0; e < 4 * RPT; ++e) dst[e] = pack2(v[e].x * is, v[e].y * is);
-            // the cell's own corners d = dx + 2 dy + 4 dz (nodes 1, 2 of rows 1, 2 of planes 1, 2) for
-            // the polish, from the threads that hold those rows: corners 2 (dy + 2 dz) and 2 (dy + 2 dz) + 1
-            // as one float4 (streaming stores: read once, by the next kernel)
+            // the cell's own corners d = dx + 2 dy + 4 dz (nodes 1, 2 of rows 1, 2 of planes 1, 2) for the
+            // polish, from the threads that hold those rows: corners 2 (dy + 2 dz) and 2 (dy + 2 dz) + 1 as
+            // one float4 (streaming stores: read once, by the next kernel)
             const int64_t s = tile * TM + r;
             if (s < n) {
                 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -869,9 +866,9 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
     head_out(tile - G);
 }
 
-// Inference, part 2: one thread per listed cell. Confident single-core interior cells get the
-// network's point polished by one Newton step; the others, and cells whose polish fails, are queued
-// (cell, descriptor, position in the list) for the plain refinement, with one atomic per workgroup and pass.
+// Inference, part 2: one thread per listed cell. Confident single-core interior cells get the network's point
+// polished by one Newton step; the others, and cells whose polish fails, are queued (cell, descriptor,
+// position in the list) for the plain refinement, with one atomic per workgroup and pass.
 __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict__ cells,
                                                const uint16_t *__restrict__ desc, const int64_t *__restrict__ count,
                                                int64_t cap, const float4 *__restrict__ net_out,
@@ -940,10 +937,12 @@ __global__ __launch_bounds__(NT) void polish_k(Geo g, const uint64_t *__restrict
             woff = (uint32_t)__shfl((int)woff, lead);
         }
         __syncthreads();
-        if (threadIdx.x == 0 && s_cnt) s_base = (int64_t)atomicAdd((unsigned long long *)fb_count, (unsigned long long)s_cnt);
+        if (threadIdx.x == 0 && s_cnt)
+            s_base = (int64_t)atomicAdd((unsigned long long *)fb_count, (unsigned long long)s_cnt);
         __syncthreads();
         if (queue) {
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
             const int64_t k = s_base + woff + rank;
             fb_cell[k] = cell;
             fb_desc[k] = (uint16_t)d;
