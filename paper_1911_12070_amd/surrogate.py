@@ -23,9 +23,10 @@ import time
 
 import numpy as np
 
-from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_MAX_STEP, MLP_NPARAMS, SAMPLE_SURROGATE, AdamParams, Extractor, dims,
-               samples_to_numpy, vx_mlp_create, vx_mlp_dataset, vx_mlp_destroy, vx_mlp_infer, vx_mlp_load,
-               vx_mlp_reserve, vx_mlp_save, vx_mlp_train_step, vx_profile_enable, vx_profile_read)
+from . import (KIND_MLP, KIND_POLISH, KIND_REFINE, MLP_MAX_STEP, MLP_NHID, MLP_NPARAMS, SAMPLE_SURROGATE,
+               AdamParams, Extractor, dims, samples_to_numpy, vx_mlp_create, vx_mlp_dataset, vx_mlp_destroy,
+               vx_mlp_infer, vx_mlp_load, vx_mlp_reserve, vx_mlp_save, vx_mlp_train_step, vx_profile_enable,
+               vx_profile_read)
 
 BAD = 8 | 16 | 32 | 64  # NONZERO_MIN, NOT_CONVERGED, NO_FACES, BAD_CELL
 
@@ -136,6 +137,9 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, m
     err = np.abs(b["off"].astype(np.float64) - a["off"].astype(np.float64)).max(axis=1)
     e_sur = err[used & ok]
     e_all = err[ok]
+    # matrix-core work of the network per cell (two hidden layers and the head, multiply-adds x 2)
+    flop = 2 * (128 * MLP_NHID + MLP_NHID * MLP_NHID + MLP_NHID * 4)
+    net_s = net_ms / max(k1, 1) * 1e-3
     return {
         "field": f"{nx}x{ny}x{nz}",
         "cells": nc,
@@ -162,6 +166,10 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, m
         "plain_wall_ms": plain_wall * 1e3,
         "surrogate_wall_ms": sur_wall * 1e3,
         "speedup_kernel": plain_ms / sur_ms,
+        "network_hidden_width": MLP_NHID,
+        "network_flop_per_cell": flop,
+        "network_tflops": flop * nc / net_s / 1e12,
+        "network_frac_of_bf16_peak": flop * nc / net_s / 2.5e15,
     }
 
 
