@@ -104,31 +104,37 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, m
     vx_mlp_reserve(ex.h, m, cap)
     plain = ex.alloc_samples(cap)
     sur = ex.alloc_samples(cap)
-    # warm up both paths, then time each with HIP events (kernel time) and wall clock
+    # warm up both paths, then time them alternately (one call of each per round, so that a drift of
+    # the clock or of the memory system over the run affects both alike): kernel time from HIP events,
+    # median over the rounds, and wall clock per call
     ex.refine(psi, out, 7, plain)
     vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur,
                  max_step=max_step)
     torch.cuda.synchronize()
-    vx_profile_enable(ex.h, True)
-    t0 = time.perf_counter()
+    t_plain, t_net, t_pol, t_fb, w_plain, w_sur = [], [], [], [], [], []
     for _ in range(reps):
+        vx_profile_enable(ex.h, True)
+        t0 = time.perf_counter()
         ex.refine(psi, out, 7, plain)
-    torch.cuda.synchronize()
-    plain_wall = (time.perf_counter() - t0) / reps
-    plain_ms, k = vx_profile_read(ex.h, KIND_REFINE)
-    plain_ms /= max(k, 1)
-    vx_profile_enable(ex.h, True)
-    t0 = time.perf_counter()
-    for _ in range(reps):
+        torch.cuda.synchronize()
+        w_plain.append(time.perf_counter() - t0)
+        ms, k = vx_profile_read(ex.h, KIND_REFINE)
+        t_plain.append(ms / max(k, 1))
+        vx_profile_enable(ex.h, True)
+        t0 = time.perf_counter()
         vx_mlp_infer(ex.h, m, d, psi, out["cells"], out["cdesc"], out["counts"][1:], cap, threshold, sur,
                      max_step=max_step)
-    torch.cuda.synchronize()
-    sur_wall = (time.perf_counter() - t0) / reps
-    net_ms, k1 = vx_profile_read(ex.h, KIND_MLP)
-    pol_ms, k3 = vx_profile_read(ex.h, KIND_POLISH)
-    fb_ms, k2 = vx_profile_read(ex.h, KIND_REFINE)
+        torch.cuda.synchronize()
+        w_sur.append(time.perf_counter() - t0)
+        t_net.append(vx_profile_read(ex.h, KIND_MLP)[0])
+        t_pol.append(vx_profile_read(ex.h, KIND_POLISH)[0])
+        t_fb.append(vx_profile_read(ex.h, KIND_REFINE)[0])
     vx_profile_enable(ex.h, False)
-    sur_ms = net_ms / max(k1, 1) + pol_ms / max(k3, 1) + fb_ms / max(k2, 1)
+    med = lambda v: float(np.median(v))
+    plain_ms = med(t_plain)
+    net_ms, pol_ms, fb_ms = med(t_net), med(t_pol), med(t_fb)
+    sur_ms = med([a + b + c for a, b, c in zip(t_net, t_pol, t_fb)])
+    plain_wall, sur_wall = med(w_plain), med(w_sur)
     a = samples_to_numpy(plain, nc)
     b = samples_to_numpy(sur, nc)
     assert np.array_equal(a["cell"], b["cell"])
@@ -139,7 +145,7 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, m
     e_all = err[ok]
     # matrix-core work of the network per cell (two hidden layers and the head, multiply-adds x 2)
     flop = 2 * (128 * MLP_NHID + MLP_NHID * MLP_NHID + MLP_NHID * 4)
-    net_s = net_ms / max(k1, 1) * 1e-3
+    net_s = net_ms * 1e-3
     return {
         "field": f"{nx}x{ny}x{nz}",
         "cells": nc,
@@ -158,9 +164,9 @@ def evaluate(ex: Extractor, m, tangle, threshold: float = 0.9, reps: int = 10, m
         "max_err_all_cells": float(e_all.max()),
         "plain_kernel_ms": plain_ms,
         "surrogate_kernel_ms": sur_ms,
-        "surrogate_net_ms": net_ms / max(k1, 1),
-        "surrogate_polish_ms": pol_ms / max(k3, 1),
-        "surrogate_fallback_ms": fb_ms / max(k2, 1),
+        "surrogate_net_ms": net_ms,
+        "surrogate_polish_ms": pol_ms,
+        "surrogate_fallback_ms": fb_ms,
         "plain_samples_per_s": nc / (plain_ms * 1e-3),
         "surrogate_samples_per_s": nc / (sur_ms * 1e-3),
         "plain_wall_ms": plain_wall * 1e3,
