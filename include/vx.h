@@ -72,7 +72,7 @@ typedef struct {
  * synchronises any other stream it used), then returns VX_ERR_CAPACITY if any call since the last
  * vx_sync_status found a list longer than its capacity -- pierced faces or cells beyond face_cap /
  * cell_cap (vx_winding, batches), listed cells beyond the sample capacity (vx_refine, vx_mlp_infer,
- * batches), training rows beyond n_cap (vx_mlp_dataset) -- with the detail in vx_last_error, and
+ * vx_mlp_predict, batches), training rows beyond n_cap (vx_mlp_dataset) -- with the detail in vx_last_error, and
  * clears the flag; VX_OK otherwise. The flag is a device word of the handle that those kernels set
  * (sticky: it is never cleared by the compute calls themselves); it travels with captured graphs. */
 vx_status vx_sync_status(vx_handle *h, vx_stream s);
@@ -310,6 +310,17 @@ vx_status vx_mlp_grad(vx_mlp *m, const uint16_t *d_feat, const float *d_target, 
                       float conf_tol, float *d_grad, float *d_loss, vx_stream s);
 /* Network outputs for rows 0..n-1: d_out[n][4] = (Z3[0], Z3[1], Z3[2], conf). */
 vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n, float *d_out, vx_stream s);
+
+/* The network alone on listed cells (for measuring it before the Newton step): d_out[i][0..3] =
+ * (Z3[0], Z3[1], Z3[2], conf) of cell d_cells[i] for i < min(*d_count, cap), from the 4x4x4 patch of
+ * nodes at offsets -1..2 around the cell (the features of vx_mlp_features; on an open axis a patch
+ * that leaves the grid takes the nearest nodes; an id outside the grid takes cell 0's patch),
+ * computed by the inference kernel of vx_mlp_infer. d_out: device, 16-byte aligned. cap must not
+ * exceed the cells reserved with vx_mlp_reserve (VX_ERR_INVALID otherwise); a count above cap is
+ * reported by vx_sync_status. Allocates nothing, does not synchronise, uses the surrogate's
+ * inference buffers (calls on one surrogate must not overlap in time). */
+vx_status vx_mlp_predict(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                         const int64_t *d_count, int64_t cap, float *d_out, vx_stream s);
 
 /* Core samples of the listed cells (as vx_refine) through the surrogate. A cell whose first
  * estimate has two pierced faces, whose patch lies inside the grid and whose conf >= conf_threshold

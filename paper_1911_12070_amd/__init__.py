@@ -37,7 +37,7 @@ EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk", "vx_batch_refine_wg",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
-           "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_infer",
+           "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_predict", "vx_mlp_infer",
            "vx_profile_enable", "vx_profile_read"]
 
 MLP_NHID = 128
@@ -194,10 +194,11 @@ def lib() -> ctypes.CDLL:
         L.vx_mlp_train_step.argtypes = [P, P, P, P, i64, ctypes.POINTER(AdamParams), P, P]
         L.vx_mlp_grad.argtypes = [P, P, P, i64, f, f, P, P, P]
         L.vx_mlp_forward.argtypes = [P, P, i64, P, P]
+        L.vx_mlp_predict.argtypes = [P, Dims, P, P, P, i64, P, P]
         L.vx_mlp_infer.argtypes = [P, Dims, P, P, P, P, i64, f, f, ctypes.POINTER(RefineParams), P, P]
         for name in ("vx_mlp_create", "vx_mlp_destroy", "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save",
                      "vx_mlp_load", "vx_mlp_dataset", "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad",
-                     "vx_mlp_forward", "vx_mlp_infer"):
+                     "vx_mlp_forward", "vx_mlp_predict", "vx_mlp_infer"):
             getattr(L, name).restype = st
         L.vx_profile_enable.argtypes = [P, i]
         L.vx_profile_enable.restype = st
@@ -517,6 +518,11 @@ def vx_mlp_grad(h, m, feat, target, n: int, conf_lambda: float, conf_tol: float,
 
 def vx_mlp_forward(h, m, feat, n: int, out, stream=None):
     _check(h, lib().vx_mlp_forward(m, _ptr(feat), int(n), _ptr(out), _stream(stream)), "vx_mlp_forward")
+
+
+def vx_mlp_predict(h, m, d: Dims, psi, cells, count, cap, out, stream=None):
+    _check(h, lib().vx_mlp_predict(m, d, _ptr(psi), _ptr(cells), _ptr(count), int(cap), _ptr(out), _stream(stream)),
+           "vx_mlp_predict")
 
 
 # default acceptance bound of the surrogate's polished point: the Newton step that would follow it (an

@@ -1273,6 +1273,41 @@ extern "C" vx_status vx_mlp_forward(vx_mlp *m, const uint16_t *d_feat, int64_t n
     return vx_hip_check(m->h, hipGetLastError(), "fwd_k launch");
 }
 
+// the network kernel over a listed-cell capacity (persistent grid: the resident workgroups, at most one
+// per 64-cell tile); its outputs go to net_out
+static void launch_net(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells, const int64_t *d_count,
+                       int64_t cap, float4 *net_out, hipStream_t hs) {
+    vx_handle *h = m->h;
+    vx_timer tm(h, hs, VX_KIND_MLP);
+    const int64_t num_cu = h->num_cu > 0 ? h->num_cu : 256;
+    const int64_t tiles = (cap + TM - 1) / TM;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu * m->infer_per_cu));
+    hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
+                       d_count, cap, net_out, m->centre, m->fb_count, vx_overflow_flag(h));
+    tm.stop();
+}
+
+extern "C" vx_status vx_mlp_predict(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
+                                    const int64_t *d_count, int64_t cap, float *d_out, vx_stream s) {
+    if (!m) return VX_ERR_INVALID;
+    vx_handle *h = m->h;
+    h->err.clear();
+    if (vx_status st = vx_check_dims(h, dims)) return st;
+    if (cap < 0) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_predict: negative capacity");
+    if (cap == 0) return VX_OK;
+    if (!d_psi || !d_cells || !d_count || !d_out)
+        return vx_fail(h, VX_ERR_INVALID, "vx_mlp_predict: null pointer argument");
+    if ((reinterpret_cast<uintptr_t>(d_out) & 15u) != 0)
+        return vx_fail(h, VX_ERR_INVALID, "vx_mlp_predict: d_out must be 16-byte aligned");
+    if (vx_status st = vx_bind(h)) return st;
+    if (cap > m->fb_cap)
+        return vx_fail(h, VX_ERR_INVALID,
+                       "vx_mlp_predict: capacity %lld exceeds the %lld cells reserved by vx_mlp_reserve",
+                       (long long)cap, (long long)m->fb_cap);
+    launch_net(m, dims, d_psi, d_cells, d_count, cap, reinterpret_cast<float4 *>(d_out), (hipStream_t)s);
+    return vx_hip_check(h, hipGetLastError(), "vx_mlp_predict launch");
+}
+
 extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, const uint64_t *d_cells,
                                   const uint16_t *d_cell_desc, const int64_t *d_count, int64_t cap, float conf_threshold,
                                   float max_step, const vx_refine_params *p, vx_sample *d_out, vx_stream s) {
@@ -1292,13 +1327,8 @@ extern "C" vx_status vx_mlp_infer(vx_mlp *m, vx_dims dims, const void *d_psi, co
                        (long long)cap, (long long)m->fb_cap);
     if (!(max_step >= 0.f)) return vx_fail(h, VX_ERR_INVALID, "vx_mlp_infer: max_step must be >= 0");
     hipStream_t hs = (hipStream_t)s;
-    vx_timer tm(h, hs, VX_KIND_MLP);
     const int64_t num_cu = h->num_cu > 0 ? h->num_cu : 256;
-    const int64_t tiles = (cap + TM - 1) / TM;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(tiles, num_cu * m->infer_per_cu));
-    hipLaunchKernelGGL(infer_net_k, dim3((unsigned)grid), dim3(NTI), 0, hs, net_of(m), geo_of(dims, d_psi), d_cells,
-                       d_count, cap, m->net_out, m->centre, m->fb_count, vx_overflow_flag(h));
-    tm.stop();
+    launch_net(m, dims, d_psi, d_cells, d_count, cap, m->net_out, hs);
     vx_timer tp(h, hs, VX_KIND_POLISH);
     const int64_t pgrid = std::max<int64_t>(1, std::min<int64_t>((cap + NT - 1) / NT, (int64_t)POLISH_WG_PER_CU * num_cu));
     hipLaunchKernelGGL(polish_k, dim3((unsigned)pgrid), dim3(NT), 0, hs, geo_of(dims, d_psi), d_cells,

@@ -213,6 +213,57 @@ def test_dataset_rows(ex):
     assert e.value.status == VX_ERR_CAPACITY and "n_cap" in str(e.value)
 
 
+def test_predict_matches_oracle_network(ex):
+    """The inference kernel's own predictions (vx_mlp_predict) against the oracle network on the
+    oracle's features of every listed cell of a periodic field, the cells at the x seams (whose patch
+    rows wrap) included: the patch gather, the feature scaling and both layers of the inference
+    kernel, to the BF16 rounding of the activations. A capacity below the count writes exactly the
+    first cap rows and sets the sticky capacity status; bad arguments are rejected."""
+    import torch
+    from paper_1911_12070_amd import VX_ERR_CAPACITY, VxError, dims, vx_mlp_destroy, vx_mlp_predict, vx_sync_status
+    psi_np, psi, out = field_cells(ex, seed=25, shape=(64, 48, 40))
+    nc = int(out["counts"][1])
+    nz, ny, nx = psi_np.shape
+    d = dims(nx, ny, nz, 7)
+    P = vxinputs.mlp_init(12)
+    P["W3"] = P["W3"] * 10.0
+    m = make_mlp(ex, P)
+    pred = torch.zeros((nc, 4), dtype=torch.float32, device="cuda")
+    vx_mlp_predict(ex.h, m, d, psi, out["cells"], out["counts"][1:], nc, pred)
+    torch.cuda.synchronize()
+    o = pred.cpu().numpy().astype(np.float64)
+    cells = out["cells"][:nc].cpu().numpy()
+    X = np.stack([M.bf16(M.features(*oracle.gather_patch(psi_np, int(c)))) for c in cells])
+    Z3 = M.forward(bf16_params(P), X)["Z3"]
+    seam = ((cells % nx) == 0) | ((cells % nx) >= nx - 2)
+    scale = np.abs(Z3[:, :3]).max()
+    err = np.abs(o[:, :3] - Z3[:, :3]).max(axis=1) / scale
+    cerr = np.abs(o[:, 3] - M.sigmoid(Z3[:, 3]))
+    log(f"predict: {nc} cells ({seam.sum()} at the x seams): max rel err {err.max():.2e} "
+        f"(seams {err[seam].max():.2e}), conf err {cerr.max():.2e}")
+    assert seam.sum() > 10
+    assert err.max() < 2e-2 and cerr.max() < 1e-2
+    # capacity below the count: the first cap rows (bit for bit), the rest untouched, the flag set
+    try:
+        vx_sync_status(ex.h)
+    except VxError:
+        pass
+    part = torch.full((nc, 4), 7.0, dtype=torch.float32, device="cuda")
+    cap = nc // 2
+    vx_mlp_predict(ex.h, m, d, psi, out["cells"], out["counts"][1:], cap, part)
+    torch.cuda.synchronize()
+    q = part.cpu().numpy()
+    assert np.array_equal(q[:cap], pred.cpu().numpy()[:cap]) and (q[cap:] == 7.0).all()
+    with pytest.raises(VxError) as e:
+        vx_sync_status(ex.h)
+    assert e.value.status == VX_ERR_CAPACITY
+    with pytest.raises(VxError):  # more cells than reserved
+        vx_mlp_predict(ex.h, m, d, psi, out["cells"], out["counts"][1:], (1 << 16) + 1, pred)
+    with pytest.raises(VxError):  # misaligned output
+        vx_mlp_predict(ex.h, m, d, psi, out["cells"], out["counts"][1:], 1, pred.view(-1)[1:])
+    vx_mlp_destroy(ex.h, m)
+
+
 def test_infer_fallback_and_surrogate(ex, tmp_path):
     import torch
     from paper_1911_12070_amd import (SAMPLE_SURROGATE, dims, samples_to_numpy, vx_mlp_destroy, vx_mlp_features,
