@@ -248,9 +248,11 @@ vx_status vx_refine_noalloc(vx_dims dims, const void *d_psi, const uint64_t *d_c
  * core sample minus the cell's first estimate x0 (mean of its pierced-face centres, cell units);
  * conf = 1 / (1 + exp(-Z3[3])).
  * Arithmetic: BF16 matrix operands (features, weights, activations) on the matrix cores with FP32
- * accumulation; biases, master weights, Adam moments and the loss in FP32; gelu and its
- * derivative read from FP32 tables of the exact function (erff/expf at creation, 1/64 spacing on
- * [-8, 8], linear interpolation, error below 3e-5; identity / zero outside).
+ * accumulation; biases, master weights, Adam moments and the loss in FP32; in training, gelu and
+ * its derivative read from FP32 tables of the exact function (erff/expf at creation, 1/64 spacing
+ * on [-8, 8], linear interpolation, error below 3e-5; identity / zero outside); in inference, gelu
+ * from a fitted closed form x sigmoid(x (a + b x^2 + c x^4)) (x clamped to [-8, 8] inside the
+ * sigmoid), error below 3e-5 as well.
  * Parameters (host layout, VX_MLP_NPARAMS floats): W1 row-major, b1, W2, b2, W3, b3.
  * Training loss per sample: |Z3[0..2] - t|^2 + lambda * (log(1 + exp(Z3[3])) - y Z3[3]), y = 1 if
  * the current prediction is within conf_tol of t on every axis (no gradient through y); the mean

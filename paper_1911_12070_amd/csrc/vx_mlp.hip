@@ -76,6 +76,19 @@ __device__ __forceinline__ float tab(const float2 *t, float x) {
     return fmaf(u, e.y, e.x);
 }
 
+// gelu for the inference kernel without a table: Phi(x) ~ sigmoid(x (a + b x^2 + c x^4)) with a = 1.5950158,
+// b = 0.0740113, c = -7.0303e-4 (fitted for the least maximum of |x sigmoid(..) - x Phi(x)| over all x, which
+// is 2.6e-5 here, as small as the table's error), evaluated as x / (1 + 2^(xc q(xc^2))) with q = -(a + b t +
+// c t^2) log2(e) and xc = x clamped to [-8, 8] (beyond, the x^4 term would turn the sign; there the result is
+// x or 0 to FP32 precision). One exp2 and one reciprocal, hardware approximations within an ulp or two; no
+// LDS traffic, which the table's scattered lookups cost the network kernel.
+__device__ __forceinline__ float gelu_fit(float x) {
+    const float xc = __builtin_amdgcn_fmed3f(x, -8.f, 8.f);
+    const float t = xc * xc;
+    const float q = fmaf(fmaf(t, 1.014263020e-03f, -1.067757234e-01f), t, -2.301121235e+00f);
+    return x * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(xc * q));
+}
+
 struct Geo {
     const float2 *psi;
     int nx, ny, nz, px, py, pz;
@@ -681,15 +694,18 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // its own 32 features by the matching rows of W3 and the NH / 32 partial heads of a cell are summed in LDS,
 // by wavefront 0 after the next tile's first barrier: two barriers per tile (features, first layer). The
 // barriers wait for LDS traffic only, so that the patch nodes of the next tile (and the cell ids of the one
-// after) stay in flight across them. Output per cell: (Z3[0], Z3[1], Z3[2], conf).
-__global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t *__restrict__ cells,
-                                                   const int64_t *__restrict__ count, int64_t cap, float4 *net_out,
-                                                   float4 *centre, int64_t *fb_count, unsigned long long *flag) {
+// after) stay in flight across them. Each layer runs block by block of 16 cells (all k-steps of a block,
+// then its gelu epilogue), so that a block's epilogue can issue beside the next block's matrix products and
+// only one A fragment is live at a time; gelu is the fitted closed form (gelu_fit), so the CU's LDS carries
+// operands only. Registers are held to what three workgroups per CU allow (168). Output per cell: (Z3[0],
+// Z3[1], Z3[2], conf).
+__global__ __launch_bounds__(NTI) __attribute__((amdgpu_waves_per_eu(3, 3))) void infer_net_k(
+    Net N, Geo g, const uint64_t *__restrict__ cells, const int64_t *__restrict__ count, int64_t cap,
+    float4 *net_out, float4 *centre, int64_t *fb_count, unsigned long long *flag) {
     constexpr int NW = NTI / 64;
     static_assert(NW * 32 == NH && (GPC == 4 || GPC == 8), "one wavefront per 32 hidden features");
     __shared__ __attribute__((aligned(16))) __bf16 sX[TM * XP];
     __shared__ __attribute__((aligned(16))) __bf16 sH[TM * HP];
-    __shared__ float2 sg[GT];
     __shared__ __attribute__((aligned(16))) float sB[2 * NH];          // b1 then b2
     __shared__ __attribute__((aligned(16))) float sP[NW * TM * NOUT];  // partial heads [wavefront][cell][4]
     const int64_t cnt = *count;
@@ -702,7 +718,6 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
     if ((int64_t)blockIdx.x >= ntiles) return;  // uniform per workgroup
     const int t = threadIdx.x, l = t & 63, w = t >> 6, n0 = 32 * w, q4 = 4 * (l >> 4);
     const int64_t G = gridDim.x;
-    for (int i = t; i < GT; i += NTI) sg[i] = N.gelu[i];
     sB[t] = N.master[t < NH ? OFF_B1 + t : OFF_B2 + t - NH];
     bf16x8 b1[2][NK1], b2[2][NK2], a3;
 #pragma unroll
@@ -815,24 +830,21 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) acc[rr][c] = b;
         }
-#pragma unroll
-        for (int kk = 0; kk < NK1; ++kk) {
-            bf16x8 a[4];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) a[rr] = ld8(sX + (16 * rr + (l & 15)) * XP + 32 * kk + 8 * (l >> 4));
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b1[c][kk], a[rr], acc[rr][c]);
-        }
         // sH is free: the previous tile's second layer ended before this tile's first barrier
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int rr = 0; rr < 4; ++rr) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
+            for (int kk = 0; kk < NK1; ++kk) {
+                const bf16x8 a = ld8(sX + (16 * rr + (l & 15)) * XP + 32 * kk + 8 * (l >> 4));
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b1[c][kk], a, acc[rr][c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
                 *(uint2 *)(sH + (16 * rr + (l & 15)) * HP + n0 + 16 * c + q4) =
-                    make_uint2(pack2(tab(sg, acc[rr][c][0]), tab(sg, acc[rr][c][1])),
-                               pack2(tab(sg, acc[rr][c][2]), tab(sg, acc[rr][c][3])));
+                    make_uint2(pack2(gelu_fit(acc[rr][c][0]), gelu_fit(acc[rr][c][1])),
+                               pack2(gelu_fit(acc[rr][c][2]), gelu_fit(acc[rr][c][3])));
+        }
         lds_barrier();  // H1 complete
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -840,24 +852,20 @@ __global__ __launch_bounds__(NTI) void infer_net_k(Net N, Geo g, const uint64_t 
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) acc[rr][c] = b;
         }
-#pragma unroll
-        for (int kk = 0; kk < NK2; ++kk) {
-            bf16x8 a[4];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) a[rr] = ld8(sH + (16 * rr + (l & 15)) * HP + 32 * kk + 8 * (l >> 4));
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b2[c][kk], a[rr], acc[rr][c]);
-        }
         // H2 never leaves registers: partial head of this wavefront's 32 features; lanes 0..15 end
         // with outputs 0..3 of cell 16rr + l (the rows of the other lanes are the zero padding)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const uint4 hv = make_uint4(pack2(tab(sg, acc[rr][0][0]), tab(sg, acc[rr][0][1])),
-                                        pack2(tab(sg, acc[rr][0][2]), tab(sg, acc[rr][0][3])),
-                                        pack2(tab(sg, acc[rr][1][0]), tab(sg, acc[rr][1][1])),
-                                        pack2(tab(sg, acc[rr][1][2]), tab(sg, acc[rr][1][3])));
+#pragma unroll
+            for (int kk = 0; kk < NK2; ++kk) {
+                const bf16x8 a = ld8(sH + (16 * rr + (l & 15)) * HP + 32 * kk + 8 * (l >> 4));
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[rr][c] = mfma(b2[c][kk], a, acc[rr][c]);
+            }
+            const uint4 hv = make_uint4(pack2(gelu_fit(acc[rr][0][0]), gelu_fit(acc[rr][0][1])),
+                                        pack2(gelu_fit(acc[rr][0][2]), gelu_fit(acc[rr][0][3])),
+                                        pack2(gelu_fit(acc[rr][1][0]), gelu_fit(acc[rr][1][1])),
+                                        pack2(gelu_fit(acc[rr][1][2]), gelu_fit(acc[rr][1][3])));
             const f32x4 z = mfma(a3, __builtin_bit_cast(bf16x8, hv), f32x4{0.f, 0.f, 0.f, 0.f});
             if (l < 16) *(f32x4 *)(sP + (w * TM + 16 * rr + l) * NOUT) = z;
         }
