@@ -46,19 +46,52 @@ struct Dual {
     int64_t nboundary = 0;
 };
 
-// Builds the graph; returns VX_ERR_INVALID (with *bad = the offending input position) for duplicate
-// cells, cells outside the grid, or a pierced face whose neighbour cell is not listed.
+// Index of the first entry >= id in the ascending array a (a.size() if none), for an id near a[v]:
+// a galloping search outward from v, then a binary search in the last interval. Neighbours along x
+// are the next entries, along y a few entries away, so most lookups touch a few nearby lines.
+inline int64_t find_from(const std::vector<uint64_t> &a, int64_t v, uint64_t id) {
+    const int64_t n = (int64_t)a.size();
+    int64_t lo, hi;  // the answer lies in [lo + 1, hi]
+    if (id > a[v]) {
+        lo = v;
+        hi = v + 1;
+        for (int64_t step = 1; hi < n && a[hi] < id; step <<= 1) {
+            lo = hi;
+            hi = v + 2 * step;
+        }
+        hi = std::min(hi, n);
+    } else {
+        hi = v;
+        lo = v - 1;
+        for (int64_t step = 1; lo >= 0 && a[lo] >= id; step <<= 1) {
+            hi = lo;
+            lo = v - 2 * step;
+        }
+        lo = std::max(lo, (int64_t)-1);
+    }
+    return std::lower_bound(a.begin() + (lo + 1), a.begin() + hi, id) - a.begin();
+}
+
+// Builds the graph; returns VX_ERR_INVALID (with *bad = the offending input position: for a duplicate
+// cell the later of the two) for duplicate cells, cells outside the grid, or a pierced face whose
+// neighbour cell is not listed.
 inline vx_status build_dual(const vx_dims &d, const uint64_t *cells, const uint16_t *desc, int64_t n, Dual &g,
                             int64_t *bad) {
     g.n = n;
-    g.input.resize(n);
-    for (int64_t i = 0; i < n; ++i) g.input[i] = i;
-    std::sort(g.input.begin(), g.input.end(), [&](int64_t a, int64_t b) { return cells[a] < cells[b]; });
-    g.cell.resize(n);
+    {
+        std::vector<std::pair<uint64_t, int64_t>> key((size_t)n);
+        for (int64_t i = 0; i < n; ++i) key[i] = {cells[i], i};
+        std::sort(key.begin(), key.end());
+        g.input.resize(n);
+        g.cell.resize(n);
+        for (int64_t v = 0; v < n; ++v) {
+            g.cell[v] = key[v].first;
+            g.input[v] = key[v].second;
+        }
+    }
     g.desc.resize(n);
     const uint64_t N = (uint64_t)d.nx * (uint64_t)d.ny * (uint64_t)d.nz;
     for (int64_t v = 0; v < n; ++v) {
-        g.cell[v] = cells[g.input[v]];
         g.desc[v] = desc[g.input[v]];
         if (g.cell[v] >= N || (v > 0 && g.cell[v] == g.cell[v - 1])) {
             *bad = g.input[v];
@@ -90,12 +123,12 @@ inline vx_status build_dual(const vx_dims &d, const uint64_t *cells, const uint1
                 continue;
             }
             const uint64_t id = (uint64_t)q[0] + (uint64_t)d.nx * ((uint64_t)q[1] + (uint64_t)d.ny * (uint64_t)q[2]);
-            const auto it = std::lower_bound(g.cell.begin(), g.cell.end(), id);
-            if (it == g.cell.end() || *it != id) {
+            const int64_t at = find_from(g.cell, v, id);
+            if (at == n || g.cell[at] != id) {
                 *bad = g.input[v];
                 return VX_ERR_INVALID;
             }
-            g.nbr.push_back(it - g.cell.begin());
+            g.nbr.push_back(at);
             // winding about +e_a; outward through the +a face it is w, through the -a face -w
             g.out.push_back((int8_t)(side ? w : -w));
         }
@@ -184,23 +217,31 @@ struct PGraph {
     std::vector<int64_t> comp;    // component (of the original graph) of each node
 };
 
+// Undirected adjacency from vertex pairs: each vertex's neighbours ascending, without duplicates or
+// self loops (bucketed by vertex, then each short list sorted).
 inline void csr_from_pairs(int64_t n, std::vector<std::pair<int64_t, int64_t>> &pairs, PGraph &g) {
-    std::vector<std::pair<int64_t, int64_t>> both;
-    both.reserve(2 * pairs.size());
+    std::vector<int64_t> first(n + 1, 0);
     for (auto &e : pairs)
         if (e.first != e.second) {
-            both.emplace_back(e.first, e.second);
-            both.emplace_back(e.second, e.first);
+            ++first[e.first + 1];
+            ++first[e.second + 1];
         }
-    std::sort(both.begin(), both.end());
-    both.erase(std::unique(both.begin(), both.end()), both.end());
+    for (int64_t v = 0; v < n; ++v) first[v + 1] += first[v];
+    std::vector<int64_t> all((size_t)first[n]), fill(first.begin(), first.end() - 1);
+    for (auto &e : pairs)
+        if (e.first != e.second) {
+            all[fill[e.first]++] = e.second;
+            all[fill[e.second]++] = e.first;
+        }
     g.start.assign(n + 1, 0);
-    g.nbr.resize(both.size());
-    for (size_t i = 0; i < both.size(); ++i) {
-        ++g.start[both[i].first + 1];
-        g.nbr[i] = both[i].second;
+    g.nbr.clear();
+    g.nbr.reserve(all.size());
+    for (int64_t v = 0; v < n; ++v) {
+        const auto b = all.begin() + first[v], e = all.begin() + first[v + 1];
+        std::sort(b, e);
+        g.nbr.insert(g.nbr.end(), b, std::unique(b, e));
+        g.start[v + 1] = (int64_t)g.nbr.size();
     }
-    for (int64_t v = 0; v < n; ++v) g.start[v + 1] += g.start[v];
 }
 
 // One reduction pass; returns the reduced graph.
