@@ -15,7 +15,8 @@ all of them (median of 5 runs each), with the host's CPU model and thread count.
 
 With --workload series_64 it measures batching instead: 64 frames of uneven size (128^3 to 384^3,
 one 1024-wave tangle advanced in time, 1.32e9 cells in all), winding + compaction + refinement of
-every frame in one HIP graph launch per step (z-chunk depths autotuned before timing).
+every frame in one HIP graph launch per step (z-chunk depths and the resident workgroups per CU of
+the winding and the refinement autotuned before timing).
 """
 from __future__ import annotations
 
@@ -313,6 +314,7 @@ def bench_series(args):
     batch.autotune(None, stream)
     tuned = {t.dims[0]: batch.zchunk(f) for f, t in enumerate(tangles)}
     refine_wg = batch.refine_wg()
+    wind_wg = batch.wind_wg()
     for _ in range(args.warmup):
         batch.launch(stream)
     torch.cuda.synchronize()
@@ -363,6 +365,7 @@ def bench_series(args):
             "cells": cells,
             "frames_per_size": {str(k): series.sizes.count(k) for k in sorted(set(series.sizes))},
             "zchunk_per_size": {str(k): v for k, v in sorted(tuned.items())},
+            "winding_workgroups_per_cu": wind_wg,
             "refine_workgroups_per_cu": refine_wg,
             "pierced_faces": nf_all,
             "pierced_cells": nc_all,

@@ -381,15 +381,19 @@ vx_status vx_batch_zchunk(const vx_batch *b, int frame, int *zchunk);
 /* Resident refinement workgroups per CU the batch launches: 0 until vx_batch_autotune has chosen
  * one (the library's default is used), then the tuned value. */
 vx_status vx_batch_refine_wg(const vx_batch *b, int *wg_per_cu);
+/* Resident winding workgroups per CU the batch launches: 0 until vx_batch_autotune has chosen (as
+ * many as fit), then the tuned value. */
+vx_status vx_batch_wind_wg(const vx_batch *b, int *wg_per_cu);
 /* Autotune the z-chunk depth of every distinct frame shape for this batch, by coordinate descent
  * over {8, 16, 32, 64, 128} (values above nz dropped) in two sweeps over the shapes, timing the
  * batched winding launch with HIP events on s (median of 7 after one warm-up); synchronises s.
  * cache_path (nullable) is a JSON
  * file of earlier results, one object per line: {"kind": "batch", "dims": [nx, ny, nz],
  * "periodic": p, "zchunk": z}; entries found there are used without timing, new results are
- * appended. Then, on the lists of one winding with those depths, the refinement's resident
- * workgroups per CU (2 .. what fits), timed the same way, not cached. The graph is captured again
- * with the choices. */
+ * appended. Then, with those depths, the winding's resident workgroups per CU (as many as fit and
+ * one or two fewer, set by the workgroup's LDS) and, on the lists of one winding, the refinement's
+ * resident workgroups per CU (2 .. what fits), timed the same way, not cached. The graph is captured
+ * again with the choices. */
 vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_stream s);
 vx_status vx_batch_destroy(vx_batch *b);
 

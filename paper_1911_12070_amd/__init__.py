@@ -35,6 +35,7 @@ EXPORTS = ["vx_sync_status", "vx_version", "vx_create", "vx_destroy", "vx_status
            "vx_curves_build", "vx_curves_info", "vx_curves_get", "vx_curves_destroy",
            "vx_density", "vx_mean_density",
            "vx_batch_create", "vx_batch_launch", "vx_batch_launch_eager", "vx_batch_zchunk", "vx_batch_refine_wg",
+           "vx_batch_wind_wg",
            "vx_batch_autotune", "vx_batch_destroy", "vx_autotune", "vx_mlp_create", "vx_mlp_destroy",
            "vx_mlp_reserve", "vx_mlp_get_params", "vx_mlp_set_params", "vx_mlp_save", "vx_mlp_load", "vx_mlp_dataset",
            "vx_mlp_features", "vx_mlp_train_step", "vx_mlp_grad", "vx_mlp_forward", "vx_mlp_predict", "vx_mlp_infer",
@@ -175,6 +176,8 @@ def lib() -> ctypes.CDLL:
         L.vx_batch_zchunk.restype = st
         L.vx_batch_refine_wg.argtypes = [P, ctypes.POINTER(i)]
         L.vx_batch_refine_wg.restype = st
+        L.vx_batch_wind_wg.argtypes = [P, ctypes.POINTER(i)]
+        L.vx_batch_wind_wg.restype = st
         L.vx_batch_autotune.argtypes = [P, ctypes.c_char_p, P]
         L.vx_batch_autotune.restype = st
         L.vx_batch_destroy.argtypes = [P]
@@ -432,6 +435,12 @@ def vx_batch_zchunk(h, b, frame: int) -> int:
 def vx_batch_refine_wg(h, b) -> int:
     w = ctypes.c_int()
     _check(h, lib().vx_batch_refine_wg(b, ctypes.byref(w)), "vx_batch_refine_wg")
+    return w.value
+
+
+def vx_batch_wind_wg(h, b) -> int:
+    w = ctypes.c_int()
+    _check(h, lib().vx_batch_wind_wg(b, ctypes.byref(w)), "vx_batch_wind_wg")
     return w.value
 
 

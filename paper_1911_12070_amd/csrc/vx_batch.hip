@@ -28,6 +28,8 @@ struct vx_batch {
     vx_refine_params p{};
     std::vector<int> zc;  // planes per z-chunk of each frame
     int ref_wg = 0;       // resident refinement workgroups per CU (0: the library's default)
+    int wind_wg = 0;      // resident winding workgroups per CU (0: as many as fit)
+    int wind_pad = 0;     // the dynamic LDS per winding workgroup that caps them there
     vx_wind_args *d_wargs = nullptr;
     int *d_tile_start = nullptr;
     vx_ref_frame *d_rframes = nullptr;
@@ -172,7 +174,8 @@ vx_status upload(vx_batch *b) {
 }
 
 vx_status enqueue_wind(vx_batch *b, hipStream_t s) {
-    return vx_wind_batch_enqueue(b->h, b->d_wargs, b->d_tile_start, (int)b->frames.size(), b->total_tiles, s);
+    return vx_wind_batch_enqueue(b->h, b->d_wargs, b->d_tile_start, (int)b->frames.size(), b->total_tiles,
+                                 b->wind_pad, s);
 }
 
 // timed: record the winding and refinement launches separately (eager launches only, never inside
@@ -305,6 +308,12 @@ extern "C" vx_status vx_batch_refine_wg(const vx_batch *b, int *wg_per_cu) {
     return VX_OK;
 }
 
+extern "C" vx_status vx_batch_wind_wg(const vx_batch *b, int *wg_per_cu) {
+    if (!b || !wg_per_cu) return VX_ERR_INVALID;
+    *wg_per_cu = b->wind_wg;
+    return VX_OK;
+}
+
 extern "C" vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_stream s) {
     if (!b) return VX_ERR_INVALID;
     vx_handle *h = b->h;
@@ -357,6 +366,26 @@ extern "C" vx_status vx_batch_autotune(vx_batch *b, const char *cache_path, vx_s
             append_cache(cache_path, "batch", k, zc, best_ms[k]);
         }
     if (st == VX_OK) st = upload(b);
+    // resident winding workgroups per CU with the chosen depths: as many as fit and one or two fewer
+    // (fewer keep more of the halo lines that neighbouring tiles share in L2, more hide more latency)
+    if (st == VX_OK) {
+        const int top = vx_wind_batch_max_wg(h);
+        int best_wg = 0, best_pad = 0;
+        double best = 1e30;
+        for (int wg = top; st == VX_OK && wg >= std::max(1, top - 2); --wg) {
+            b->wind_pad = wg == top ? 0 : vx_wind_batch_pad(h, wg);
+            double ms = 0.0;
+            st = time_median(h, hs, 7, [&] { return enqueue_wind(b, hs); }, &ms);
+            if (st == VX_OK && ms < best) {
+                best = ms;
+                best_wg = wg;
+                best_pad = b->wind_pad;
+            }
+        }
+        if (top < 1 && st == VX_OK) st = vx_fail(h, VX_ERR_DEVICE, "vx_batch_autotune: winding occupancy query failed");
+        b->wind_wg = best_wg;
+        b->wind_pad = best_pad;
+    }
     // resident refinement workgroups per CU, on the lists of one winding with the chosen depths
     if (st == VX_OK && b->n_ref > 0) {
         st = enqueue_wind(b, hs);

@@ -122,8 +122,12 @@ vx_status vx_wind_enqueue(vx_handle *h, const vx_wind_args &A, int64_t ntiles, h
 // planes per z-chunk the handle uses for a single grid of these dims
 int vx_wind_zc_for(vx_handle *h, const vx_dims &d);
 // one launch over the tiles of several grids (tables in device memory; tile_start[nframes] = total)
+// (lds_pad: dynamic LDS per workgroup, which caps the resident workgroups per CU; 0 = as many as fit)
 vx_status vx_wind_batch_enqueue(vx_handle *h, const vx_wind_args *d_frames, const int *d_tile_start, int nframes,
-                                int64_t total_tiles, hipStream_t s);
+                                int64_t total_tiles, int lds_pad, hipStream_t s);
+// resident batch-winding workgroups per CU without a pad (-1 on error), and the pad that leaves N
+int vx_wind_batch_max_wg(vx_handle *h);
+int vx_wind_batch_pad(vx_handle *h, int wg_per_cu);
 // one launch refining the listed cells of several grids (table in device memory)
 // wg_per_cu > 0: resident refinement workgroups per CU to launch (capped by what fits); 0: the default
 vx_status vx_refine_batch_enqueue(vx_handle *h, const vx_ref_frame *d_frames, int nframes, int64_t total_cap,

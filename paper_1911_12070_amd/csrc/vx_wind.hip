@@ -645,11 +645,26 @@ vx_status vx_wind_launch(vx_handle *h, const vx_dims &d, const void *psi, const 
     return vx_wind_enqueue(h, A, nblocks, s);
 }
 
+int vx_wind_batch_max_wg(vx_handle *h) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, wind_batch_k, 64, 0) != hipSuccess || nb < 1) return -1;
+    return nb;
+}
+
+int vx_wind_batch_pad(vx_handle *h, int wg_per_cu) {
+    hipFuncAttributes fa;
+    if (wg_per_cu <= 0 || h->lds_per_cu <= 0 || hipFuncGetAttributes(&fa, (const void *)wind_batch_k) != hipSuccess)
+        return 0;
+    // per-workgroup LDS just above 1/(N+1) of the CU's: N fit, N+1 do not (no pad where LDS allows only N)
+    return std::max(0, h->lds_per_cu / (wg_per_cu + 1) + 512 - (int)fa.sharedSizeBytes);
+}
+
 vx_status vx_wind_batch_enqueue(vx_handle *h, const vx_wind_args *d_frames, const int *d_tile_start, int nframes,
-                                int64_t total_tiles, hipStream_t s) {
+                                int64_t total_tiles, int lds_pad, hipStream_t s) {
     if (total_tiles > 2147483647LL) return vx_fail(h, VX_ERR_UNSUPPORTED, "winding batch: too many tiles");
     hipLaunchKernelGGL(zero_batch_counts_k, dim3((nframes + 63) / 64), dim3(64), 0, s, d_frames, nframes);
     if (total_tiles > 0)
-        hipLaunchKernelGGL(wind_batch_k, dim3((unsigned)total_tiles), dim3(64), 0, s, d_frames, d_tile_start, nframes);
+        hipLaunchKernelGGL(wind_batch_k, dim3((unsigned)total_tiles), dim3(64), lds_pad, s, d_frames, d_tile_start,
+                           nframes);
     return vx_hip_check(h, hipGetLastError(), "wind_batch_k launch");
 }

@@ -216,6 +216,11 @@ class Batch:
         from . import vx_batch_refine_wg
         return vx_batch_refine_wg(self.ex.h, self.b)
 
+    def wind_wg(self) -> int:
+        """Resident winding workgroups per CU of the batch (0 until autotuned: as many as fit)."""
+        from . import vx_batch_wind_wg
+        return vx_batch_wind_wg(self.ex.h, self.b)
+
     def zchunk(self, frame: int) -> int:
         from . import vx_batch_zchunk
         return vx_batch_zchunk(self.ex.h, self.b, frame)

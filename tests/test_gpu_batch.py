@@ -117,11 +117,12 @@ def test_batch_autotune_and_cache(ex, tmp_path):
     batch.launch(graph=False)
     ref = results(batch)
     cache = str(tmp_path / "tune.jsonl")
-    assert batch.refine_wg() == 0  # the default until tuned
+    assert batch.refine_wg() == 0 and batch.wind_wg() == 0  # the defaults until tuned
     batch.autotune(cache)
     chosen = [batch.zchunk(f) for f in range(len(SHAPES))]
-    log(f"tuned z-chunks {chosen}, refinement workgroups per CU {batch.refine_wg()}")
-    assert 2 <= batch.refine_wg() <= 8
+    log(f"tuned z-chunks {chosen}, winding workgroups per CU {batch.wind_wg()}, refinement workgroups per CU "
+        f"{batch.refine_wg()}")
+    assert 2 <= batch.refine_wg() <= 8 and 1 <= batch.wind_wg() <= 16
     for z, (_, _, nz, _) in zip(chosen, SHAPES):
         assert z in CANDIDATES
     lines = open(cache).read().strip().splitlines()
